@@ -1,0 +1,92 @@
+"""FP64 oracle of the light-curve fit served by the library.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/salt64.py``).
+
+The paper's example drivers fit the free SALT parameters x0, x1, t0, c of one
+supernova to its photometry by gradient-based optimisation (section
+"Implementation", the two example scripts).  The served fit is a
+Levenberg-Marquardt damped Gauss-Newton iteration, written here step by step:
+
+* unknowns q = (t0, ln x0, x1, c); z is given and held fixed;
+* residuals r_i = d_i - f_i(q), weights W_i = 1/sigma_i^2, chi2 = sum W r^2;
+* H = J^T W J and g = J^T W r with J = d f / d q, where d f/d ln x0 = x0 d f/d x0;
+* each iteration solves (H + lambda diag(H)) delta = g by Cholesky, evaluates
+  the trial q + delta, accepts it when its chi2 is finite and strictly smaller
+  (lambda /= 10), otherwise keeps q (lambda *= 10); a non-positive Cholesky
+  pivot counts as a rejected step; lambda stays within [1e-9, 1e9];
+* exactly ``iters`` iterations (default 50) after the evaluation at the
+  starting point, lambda starts at 1e-3.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .salt64 import Oracle
+
+LAMBDA_MIN, LAMBDA_MAX = 1e-9, 1e9
+
+
+def _cholesky_solve4(A, b):
+    """Solve A x = b for a symmetric 4x4 A by Cholesky; None if a pivot is not positive."""
+    n = len(b)
+    L = np.zeros((n, n))
+    for i in range(n):
+        for j in range(i + 1):
+            s = A[i, j] - np.dot(L[i, :j], L[j, :j])
+            if i == j:
+                if not (s > 0.0) or not np.isfinite(s):
+                    return None
+                L[i, i] = np.sqrt(s)
+            else:
+                L[i, j] = s / L[j, j]
+    y = np.zeros(n)
+    for i in range(n):
+        y[i] = (b[i] - np.dot(L[i, :i], y[:i])) / L[i, i]
+    x = np.zeros(n)
+    for i in reversed(range(n)):
+        x[i] = (y[i] - np.dot(L[i + 1:, i], x[i + 1:])) / L[i, i]
+    return x
+
+
+class FitOracle:
+    def __init__(self, oracle: Oracle):
+        self.o = oracle
+
+    def evaluate(self, batch, z, q, data, inv_sigma2):
+        """chi2, H (4x4) and g (4) at q = (t0, ln x0, x1, c) for a one-supernova batch."""
+        t0, lnx0, x1, c = q
+        x0 = np.exp(lnx0)
+        f, J5 = self.o.jac(batch, params=np.array([[z, t0, x0, x1, c]]))
+        J = np.stack([J5[:, 1], x0 * J5[:, 2], J5[:, 3], J5[:, 4]], axis=1)
+        r = np.asarray(data, np.float64) - f
+        w = np.asarray(inv_sigma2, np.float64)
+        chi2 = float(np.sum(w * r * r))
+        H = J.T @ (w[:, None] * J)
+        g = J.T @ (w * r)
+        return chi2, H, g
+
+    def fit(self, batch, z, theta0, data, inv_sigma2, iters=50, lambda0=1e-3):
+        """LM fit from theta0 = (t0, x0, x1, c).  Returns dict(theta, chi2, n_accept, status)."""
+        t0, x0, x1, c = [float(v) for v in theta0]
+        q = np.array([t0, np.log(x0), x1, c])
+        chi2, H, g = self.evaluate(batch, z, q, data, inv_sigma2)
+        if not np.isfinite(chi2):
+            return dict(theta=np.array([t0, x0, x1, c]), chi2=chi2, n_accept=0, status="diverged")
+        lam = lambda0
+        n_acc = 0
+        for _ in range(iters):
+            A = H + lam * np.diag(np.diag(H))
+            delta = _cholesky_solve4(A, g)
+            if delta is None:
+                lam = min(lam * 10.0, LAMBDA_MAX)
+                continue
+            qt = q + delta
+            chi2_t, H_t, g_t = self.evaluate(batch, z, qt, data, inv_sigma2)
+            if np.isfinite(chi2_t) and chi2_t < chi2:
+                q, chi2, H, g = qt, chi2_t, H_t, g_t
+                lam = max(lam * 0.1, LAMBDA_MIN)
+                n_acc += 1
+            else:
+                lam = min(lam * 10.0, LAMBDA_MAX)
+        theta = np.array([q[0], np.exp(q[1]), q[2], q[3]])
+        return dict(theta=theta, chi2=chi2, n_accept=n_acc, status="ok")

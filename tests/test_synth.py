@@ -1,0 +1,44 @@
+"""Input generators: determinism, sizes and eligibility (CPU only)."""
+import numpy as np
+
+import synth
+
+
+def test_deterministic_and_shapes():
+    a = synth.config2(n_sn=50)
+    b = synth.config2(n_sn=50)
+    assert np.array_equal(a.t, b.t) and np.array_equal(a.band, b.band) and np.array_equal(a.z, b.z)
+    assert a.sn_offsets[0] == 0 and a.sn_offsets[-1] == a.n_obs
+    n = np.diff(a.sn_offsets)
+    assert n.min() >= 20 and n.max() <= 200
+    for arr in (a.z, a.t0, a.x0, a.x1, a.c, a.t):
+        assert arr.dtype == np.float32
+    assert a.band.dtype == np.int32 and a.sn_offsets.dtype == np.int32
+
+
+def test_config2_size_and_eligibility(model, bands6):
+    b = synth.config2()
+    assert b.n_sn == 4096 and 400_000 < b.n_obs < 500_000
+    # every observation's band keeps its rest window inside the surface grid
+    for s in range(0, b.n_sn, 97):
+        lo, hi = b.sn_offsets[s], b.sn_offsets[s + 1]
+        el = set(synth.eligible_bands(float(b.z[s]), bands6, model))
+        assert set(np.unique(b.band[lo:hi])) <= el
+        # sorted by (band, t)
+        assert np.all(np.diff(b.band[lo:hi]) >= 0)
+
+
+def test_config1_and_sweep():
+    c1 = synth.config1()
+    assert c1.n_sn == 1 and c1.n_obs == 40 and set(c1.band) == {0, 1, 2, 3}
+    sw = synth.config5a(n_samples=1000)
+    assert len(sw.obs_t) == 120 and sw.samples.n_sn == 1000
+    assert sw.samples.z.max() < 0.75
+
+
+def test_make_data_sigma_rule():
+    f = np.array([1.0, -2.0, 100.0, 0.0, 5.0])
+    off = np.array([0, 3, 5])
+    d, sig, w = synth.make_data(f, off, np.zeros(5))
+    np.testing.assert_allclose(sig, np.float32([0.05, 0.1, 5.0, 0.05 * 0.05, 0.25]), rtol=1e-6)
+    np.testing.assert_allclose(d, f)
