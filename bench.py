@@ -1,0 +1,373 @@
+#!/usr/bin/env python3
+"""Benchmark of the SALT bandflux hot path on one MI355X.
+
+A step is one pass of the whole hot path over the 4,096-supernova batch
+(~450k observations, 6 bands, uneven light curves): bandflux of every
+observation, chi-square against noisy data, and the hand-written adjoint giving
+d chi2 / d(z, t0, x0, x1, c) per supernova (one fused launch).  `value` is
+observations evaluated per second (forward + adjoint) with all inputs resident
+in HBM.  Extra legs report the forward-only kernel, the persistent sweep
+(1,048,576 parameter samples x 120 observations) against the plain kernel on the
+same work, the 65,536 x 100 forward + adjoint batch, and the fit server under
+Poisson load (p50/p99 latency).  The FP64 oracle is timed on the host cores on a
+bounded sample as `cpu_baseline`.
+
+Prints one JSON line on stdout.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+METRIC = "bandflux evals/s (fwd, fwd+adjoint) vs FP64 err; p50/p99 fit latency"
+PEAK_FP32_TFLOPS = 157.3       # MI355X vector FP32 (packed); the build disables packed FP32 (half of it)
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic work per unit of the implemented algorithm (flops):
+#   per quadrature point of a (supernova, band): FWD 30, VJP 60
+#   per (point, tap) gather into the weight vectors: 1 add per weight vector (FWD 1, VJP 3)
+#   per (surface row, window column) of the row projections: FWD 2 FMA = 4, VJP 5 FMA = 10
+#   per observation: FWD 24, VJP 90
+W_PT = {"fwd": 30, "vjp": 60}
+W_TAP = {"fwd": 1, "vjp": 3}
+W_CELL = {"fwd": 4, "vjp": 10}
+W_OBS = {"fwd": 24, "vjp": 90}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------------------- work model
+
+def group_stats(batch, lam_grids, model):
+    """(points, columns, rows, observations) summed over the (supernova, band) groups of a batch,
+    formed the way the kernels form them (float32 grid coordinates)."""
+    f32 = np.float32
+    z = batch.z.astype(f32)
+    s = f32(1.0) / (f32(1.0) + z)
+    n_s = np.diff(batch.sn_offsets)
+    sn_of = np.repeat(np.arange(batch.n_sn), n_s)
+    p = (batch.t - batch.t0[sn_of]) * s[sn_of]
+    u = (p - f32(model.phase0)) * f32(1.0 / model.dphase)
+    inside = (u >= 0) & (u <= model.n_phase - 1)
+    a = np.clip(np.floor(np.where(inside, u, 0)), 0, model.n_phase - 2).astype(np.int64)
+    edge = (a == 0) | (a == model.n_phase - 2)
+    r0 = np.where(edge, a, a - 1)
+    r1 = np.where(edge, a + 1, a + 2)
+    tot = dict(points=0, cols=0, cells=0, obs=int(inside.sum()), groups=0)
+    nb = len(lam_grids)
+    key = sn_of[inside] * nb + batch.band[inside]
+    if key.size == 0:
+        return tot
+    order = np.argsort(key, kind="stable")
+    k_sorted = key[order]
+    starts = np.r_[0, np.nonzero(np.diff(k_sorted))[0] + 1]
+    keys = k_sorted[starts]
+    rlo = np.minimum.reduceat(r0[inside][order], starts)
+    rhi = np.maximum.reduceat(r1[inside][order], starts)
+    sn_g = keys // nb
+    b_g = keys % nb
+    inv_dw = f32(1.0 / model.dwave)
+    for b in range(nb):
+        m = b_g == b
+        if not m.any():
+            continue
+        lam = lam_grids[b]
+        sg = s[sn_g[m]]
+        v_lo = (f32(lam[0]) * sg - f32(model.wave0)) * inv_dw
+        v_hi = (f32(lam[-1]) * sg - f32(model.wave0)) * inv_dw
+        j0f = np.clip(np.floor(v_lo), 0, model.n_wave - 2)
+        j0l = np.clip(np.floor(v_hi), 0, model.n_wave - 2)
+        J = np.minimum(j0l + 2, model.n_wave - 1) - np.maximum(j0f - 1, 0) + 1
+        H = rhi[m] - rlo[m] + 1
+        tot["points"] += int(m.sum()) * len(lam)
+        tot["cols"] += int(J.sum())
+        tot["cells"] += int((J * H).sum())
+        tot["groups"] += int(m.sum())
+    return tot
+
+
+def algorithmic_flops(st, mode):
+    return (W_PT[mode] * st["points"] + 4 * W_TAP[mode] * st["points"] + W_CELL[mode] * st["cells"]
+            + W_OBS[mode] * st["obs"])
+
+
+def reference_flops(st, mode):
+    """Direct (unfactorised) count per observation: 16 J + 40 N forward, 40 J + 90 N adjoint,
+    with each group's J and N spread over its observations."""
+    if st["groups"] == 0:
+        return 0.0
+    mean_J = st["cols"] / st["groups"]
+    mean_N = st["points"] / st["groups"]
+    per = (16 * mean_J + 40 * mean_N) if mode == "fwd" else (40 * mean_J + 90 * mean_N)
+    return per * st["obs"]
+
+
+# ----------------------------------------------------------------------------- CPU baseline (oracle)
+
+_OR = None
+
+
+def _oracle_chunk(args):
+    batch, data, w = args
+    return _OR.chi2_grad(batch, data, w)[1].shape[0]
+
+
+def cpu_baseline(batch, model, bands, budget_s):
+    """FP64 oracle chi-square gradient on a bounded prefix of the same batch, all host cores."""
+    global _OR
+    import multiprocessing as mp
+
+    import oracle
+    _OR = oracle.Oracle(model, bands)
+    cores = min(16, os.cpu_count() or 1)
+    chunk = 16
+    n_chunks = (batch.n_sn + chunk - 1) // chunk
+    work = []
+    for c in range(n_chunks):
+        sub = batch.subset(np.arange(c * chunk, min(batch.n_sn, (c + 1) * chunk)))
+        work.append((sub, np.zeros(sub.n_obs), np.ones(sub.n_obs)))
+    ctx = mp.get_context("fork")
+    done_obs, done_sn = 0, 0
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        it = pool.imap(_oracle_chunk, work)
+        for i, _ in enumerate(it):
+            done_obs += work[i][0].n_obs
+            done_sn += work[i][0].n_sn
+            if time.perf_counter() - t0 > budget_s:
+                pool.terminate()
+                break
+    dt = time.perf_counter() - t0
+    return {"value": done_obs / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle forward+adjoint (chi2 gradient) of the first {done_sn} of the "
+                      f"{batch.n_sn} supernovae ({done_obs} observations) in {dt:.1f} s, {cores} worker processes"}
+
+
+# ----------------------------------------------------------------------------- timing helpers
+
+def time_launches(torch, fn, steps, warmup):
+    """Per-launch HIP-event durations (ms) and the wall time of `steps` back-to-back launches."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    durs = np.array([a.elapsed_time(b) for a, b in ev])
+    return durs, wall
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--sweep-samples", type=int, default=1 << 20)
+    ap.add_argument("--legs", default="fwd,sweep,big,serve")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(supernovae shard with no exchange; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+    legs = set(x for x in args.legs.split(",") if x)
+
+    model = synth.make_model()
+    bands = synth.make_bands(6)
+    truth = synth.config2()
+    ev_params = synth.perturb(truth)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: FP64 oracle on the host cores ...")
+        cpu = cpu_baseline(ev_params, model, bands, args.cpu_seconds)
+        log(f"cpu baseline: {cpu['value']:.0f} evals/s on {cpu['cores']} cores")
+
+    import torch
+    from paper_2504_08081_amd import saltbf
+    torch.cuda.set_device(0)
+    ctx = saltbf.Context.from_model(model, bands)
+    lam_grids = [saltbf.band_grid(b.wave, b.trans)[0] for b in bands]
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    def dev_batch(b):
+        return dict(z=dv(b.z), t0=dv(b.t0), x0=dv(b.x0), x1=dv(b.x1), c=dv(b.c), t=dv(b.t), band=dv(b.band),
+                    sn_offsets=dv(b.sn_offsets))
+
+    # noisy data from the GPU forward model at the true parameters (timing inputs)
+    dtrue = dev_batch(truth)
+    f_true = ctx.bandflux(**dtrue).cpu().numpy()
+    data, _, w = synth.make_data(f_true, truth.sn_offsets, synth.noise_draws(truth.n_obs))
+    D = dev_batch(ev_params)
+    D["data"], D["inv_sigma2"] = dv(data), dv(w)
+    ctx.device_check()
+    n_obs = truth.n_obs
+
+    grad = torch.empty((truth.n_sn, 5), device="cuda")
+    step = lambda: ctx.bandflux_vjp(**D, chi2=True, grad=grad)
+    log(f"main leg: fused forward+adjoint, {truth.n_sn} SN, {n_obs} obs, {args.steps} steps")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in evs:
+        a.record()
+        step()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    durs = np.array([a.elapsed_time(b) for a, b in evs])
+    ctx.device_check()
+    value = n_obs * args.steps / wall
+    st = group_stats(ev_params, lam_grids, model)
+    kern_s = float(durs.mean()) * 1e-3
+    flops = algorithmic_flops(st, "vjp")
+    achieved = flops / kern_s / 1e12
+    result = {
+        "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "fwd+adjoint chi2 gradient, 4096 SN, uneven 20-200 obs, 6 bands (configs 2/3)",
+                   "n_sn": truth.n_sn, "n_obs": n_obs, "bands": 6, "surface": "71x721", "parallelism": "none"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_sn<VJP>", "kernel_ms": float(durs.mean()),
+                     "flops_per_launch": flops, "work": st},
+        "reference_count_tflops": reference_flops(st, "vjp") / kern_s / 1e12,
+        "kernel_evals_per_s": n_obs / kern_s,
+    }
+    log(f"main: {value:.3e} evals/s, kernel {durs.mean():.4f} ms, {achieved:.2f} TFLOP/s algorithmic")
+
+    if "fwd" in legs:
+        d_nochi = {k: D[k] for k in ("z", "t0", "x0", "x1", "c", "t", "band", "sn_offsets")}
+        out = torch.empty(n_obs, device="cuda")
+        durs_f, wall_f = time_launches(torch, lambda: ctx.bandflux(**d_nochi, out=out), args.steps, args.warmup)
+        kf = float(durs_f.mean()) * 1e-3
+        result["fwd"] = {"evals_per_s": n_obs * args.steps / wall_f, "kernel_ms": float(durs_f.mean()),
+                         "kernel_evals_per_s": n_obs / kf,
+                         "algorithmic_tflops": algorithmic_flops(st, "fwd") / kf / 1e12,
+                         "reference_count_tflops": reference_flops(st, "fwd") / kf / 1e12}
+        log(f"fwd: {result['fwd']}")
+
+    if "sweep" in legs:
+        sw = synth.config5a(n_samples=args.sweep_samples)
+        smp = sw.samples
+        no = len(sw.obs_t)
+        f1 = ctx.bandflux(z=dv(np.float32([sw.theta_true[0]])), t0=dv(np.float32([sw.theta_true[1]])),
+                          x0=dv(np.float32([sw.theta_true[2]])), x1=dv(np.float32([sw.theta_true[3]])),
+                          c=dv(np.float32([sw.theta_true[4]])), t=dv(sw.obs_t), band=dv(sw.obs_band),
+                          sn_offsets=dv(np.int32([0, no]))).cpu().numpy()
+        sdata, _, sw_w = synth.make_data(f1, [0, no], synth.noise_draws(no, k=55))
+        P = dict(z=dv(smp.z), t0=dv(smp.t0), x0=dv(smp.x0), x1=dv(smp.x1), c=dv(smp.c))
+        t_o, b_o = dv(sw.obs_t), dv(sw.obs_band)
+        chi = torch.empty(smp.n_sn, device="cuda")
+        reps = 5
+        D_s = {"data": dv(sdata), "w": dv(sw_w)}
+        d_sw, wall_sw = time_launches(torch, lambda: ctx.bandflux(**P, t=t_o, band=b_o, broadcast=True, chi2=True,
+                                                                  data=D_s["data"], inv_sigma2=D_s["w"], out=chi),
+                                      reps, 1)
+        n = smp.n_sn
+        tt, bb = t_o.repeat(n), b_o.repeat(n)
+        off = torch.arange(0, (n + 1) * no, no, dtype=torch.int32, device="cuda")
+        dd, ww = D_s["data"].repeat(n), D_s["w"].repeat(n)
+        chi_pl = torch.empty(n, device="cuda")
+        d_pl, wall_pl = time_launches(torch, lambda: ctx.bandflux(**P, t=tt, band=bb, sn_offsets=off, chi2=True,
+                                                                  data=dd, inv_sigma2=ww, out=chi_pl), reps, 1)
+        same = bool(torch.equal(chi, chi_pl))
+        del tt, bb, off, dd, ww
+        evals = n * no
+        result["sweep"] = {"samples": n, "obs": no, "persistent_evals_per_s": evals / (d_sw.mean() * 1e-3),
+                           "plain_evals_per_s": evals / (d_pl.mean() * 1e-3),
+                           "persistent_ms": float(d_sw.mean()), "plain_ms": float(d_pl.mean()),
+                           "bitwise_equal": same}
+        log(f"sweep: {result['sweep']}")
+
+    if "big" in legs:
+        big = synth.config5b()
+        Db = dev_batch(synth.perturb(big, k=7))
+        fb = ctx.bandflux(**dev_batch(big)).cpu().numpy()
+        bd, _, bw = synth.make_data(fb, big.sn_offsets, synth.noise_draws(big.n_obs, k=17))
+        Db["data"], Db["inv_sigma2"] = dv(bd), dv(bw)
+        gb = torch.empty((big.n_sn, 5), device="cuda")
+        d_b, wall_b = time_launches(torch, lambda: ctx.bandflux_vjp(**Db, chi2=True, grad=gb), 10, 2)
+        result["big_fwd_adj"] = {"n_sn": big.n_sn, "n_obs": big.n_obs, "kernel_ms": float(d_b.mean()),
+                                 "evals_per_s": big.n_obs * 10 / wall_b}
+        log(f"big: {result['big_fwd_adj']}")
+        del Db
+
+    if "serve" in legs and args.serve_seconds > 0:
+        result["serving"] = serve_leg(torch, saltbf, model, bands, args.serve_seconds)
+        log(f"serving: {result['serving']}")
+
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+def serve_leg(torch, saltbf, model, bands, seconds):
+    """Poisson arrivals at 2,000 req/s: submit each request at its arrival time, collect p50/p99."""
+    rate = 2000.0
+    n_req = int(rate * (seconds + 0.5))
+    reqs = synth.config4_requests(n_req, rate=rate)
+    ctx = saltbf.Context.from_model(model, bands)
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    # true fluxes of every request in one batched forward call
+    n_s = np.array([len(r.t) for r in reqs])
+    off = np.zeros(n_req + 1, np.int32)
+    off[1:] = np.cumsum(n_s)
+    th = np.array([r.theta_true for r in reqs])
+    zz = np.float32([r.z for r in reqs])
+    f = ctx.bandflux(z=dv(zz), t0=dv(np.float32(th[:, 0])), x0=dv(np.float32(th[:, 1])),
+                     x1=dv(np.float32(th[:, 2])), c=dv(np.float32(th[:, 3])),
+                     t=dv(np.concatenate([r.t for r in reqs])), band=dv(np.concatenate([r.band for r in reqs])),
+                     sn_offsets=dv(off)).cpu().numpy()
+    normals = np.concatenate([r.normals for r in reqs])
+    data, sig, _ = synth.make_data(f, off, normals)
+    tickets = []
+    t_start = time.perf_counter()
+    for i, r in enumerate(reqs):
+        target = t_start + r.arrival
+        while True:
+            now = time.perf_counter()
+            if now >= target:
+                break
+            if target - now > 2e-4:
+                time.sleep(target - now - 1e-4)
+        lo, hi = off[i], off[i + 1]
+        tickets.append(ctx.fit_submit(r.t, r.band, data[lo:hi], sig[lo:hi], r.z, *r.theta_init))
+    res = [ctx.fit_wait(tk, 30.0) for tk in tickets]
+    stats = ctx.stats()
+    ctx.close()
+    warm = int(0.5 * rate)
+    lat = np.array([(x.t_done - x.t_submit) for x in res[warm:] if x is not None]) * 1e3
+    queue = np.array([(x.t_admit - x.t_submit) for x in res[warm:] if x is not None]) * 1e3
+    done = [x for x in res if x is not None]
+    span = max(x.t_done for x in done) - min(x.t_submit for x in done)
+    ok = sum(1 for x in done if x.status == 0)
+    return {"requests": n_req, "rate_req_s": rate, "completed_ok": ok, "fits_per_s": len(done) / span,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_queue_ms": float(queue.mean()), "ticks": stats["ticks"],
+            "mean_active_slots_per_tick": None}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,228 @@
+/*
+ * saltbf.h - C ABI of the MI355X (gfx950) SALT bandflux library.
+ *
+ * What is computed (paper, section "Implementation"):
+ *   model equation   F(p, lam) = x0 [M0(p, lam) + x1 M1(p, lam)] exp(c CL(lam)),
+ *                    free parameters x0, x1, t0, c;
+ *   bandflux         the integral over the band of F(lam) T(lam) lam / (h c),
+ *                    taken with the trapezoidal rule along wavelength;
+ *   derivatives      of the bandflux with respect to the parameters (the paper's
+ *                    differentiability claim, sections "Summary" and
+ *                    "Implementation"), here also with respect to z;
+ *   fits             of x0, x1, t0, c to a light curve (the optimisation example
+ *                    of section "Implementation").
+ * Readings where the paper is silent (one definition for the whole library):
+ *   s = 1/(1+z); phase p = (t - t0) s; amplitude A = x0 s; the surfaces are read
+ *   at rest wavelength mu = lam s of a fixed observer-frame quadrature grid lam_k
+ *   and lam/(hc) uses lam_k; M0 and M1 are interpolated by Catmull-Rom (Keys,
+ *   a = -1/2) cubic convolution, linear in the first and last cell of each axis;
+ *   a phase outside the grid gives zero flux; a band whose rest window leaves the
+ *   wavelength grid is a range error; CL(mu) = sum_n a_n r^n with
+ *   r = (mu - wave_b)/(wave_v - wave_b); the band grid has
+ *   N = ceil((U - L)/spacing) equal intervals between its first and last sample
+ *   with T interpolated linearly; h c = 6.62607015e-27 erg s x 2.99792458e18 A/s.
+ *
+ * Conventions for every call:
+ *   - Device pointers belong to the caller, must stay valid until the work on
+ *     the caller's stream has finished, and are never freed by the library.
+ *   - Host pointers are read during the call only (the library copies).
+ *   - All compute calls are asynchronous on the given HIP stream (NULL = the
+ *     legacy default stream) and never synchronise it.
+ *   - Errors are status codes; nothing crosses the ABI as an exception.
+ *     sb_last_error() returns a thread-local message for the last failing call.
+ *   - Arguments that can be checked on the host (null pointers, sizes, flags)
+ *     are checked before anything is launched.  Conditions only the device can
+ *     see (a band id >= the number of bands, a band window outside the surface,
+ *     malformed CSR offsets) turn the affected results into NaN and set a sticky
+ *     device flag that sb_device_check() reports.
+ */
+#ifndef SALTBF_H
+#define SALTBF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SB_API_VERSION 1
+#define SB_MAX_BANDS 64           /* band registry capacity per context */
+#define SB_MAX_BAND_POINTS 2048   /* quadrature nodes per band */
+#define SB_MAX_CL_DEGREE 8
+#define SB_N_PARAMS 5             /* gradient order: z, t0, x0, x1, c */
+
+typedef int32_t sb_status;
+enum {
+  SB_OK = 0,
+  SB_PENDING = 1,        /* fit not finished yet */
+  SB_CANCELLED = 2,      /* fit cancelled before it finished */
+  SB_FIT_DIVERGED = 3,   /* fit stopped: non-finite chi-square at its start */
+  SB_ERR_ARG = -1,       /* invalid argument (checked on the host) */
+  SB_ERR_RANGE = -2,     /* band window outside the surface, or bad band id / CSR (device flag) */
+  SB_ERR_DEVICE = -3,    /* HIP runtime error */
+  SB_ERR_NOMEM = -4,     /* device or host allocation failed */
+  SB_ERR_BUDGET = -5,    /* fit request larger than the whole serving budget */
+  SB_ERR_STATE = -6,     /* call not valid in the current state */
+  SB_ERR_NOTFOUND = -7   /* unknown ticket (never issued, or its result was already taken) */
+};
+
+typedef struct sb_ctx sb_ctx;   /* opaque: device copies of model and bands, scratch, fit server */
+
+/* SALT model surfaces and colour law (model equation).  m0/m1 are host arrays,
+ * row-major [n_phase][n_wave] (phase-major, wavelength contiguous), copied at
+ * sb_create.  Grid node (a, j) sits at phase phase0 + a*dphase (days) and rest
+ * wavelength wave0 + j*dwave (Angstrom).  4 <= n_phase <= 256, 4 <= n_wave <= 8192.
+ * cl_coef[0..cl_degree-1] are a_1..a_deg of CL (no constant term). */
+typedef struct {
+  int32_t n_phase, n_wave;
+  double phase0, dphase, wave0, dwave;
+  const float *m0, *m1;
+  int32_t cl_degree;
+  const double *cl_coef;
+  double cl_wave_b, cl_wave_v;
+} sb_model_desc;
+
+/* Library configuration; fill with sb_config_default() and override. */
+typedef struct {
+  double max_spacing;        /* quadrature spacing bound in Angstrom (default 5) */
+  int32_t max_obs_per_fit;   /* observations per fit request (default 256, at most 1024) */
+  int32_t max_slots;         /* fits resident on the device at once (default 1024) */
+  int64_t hbm_budget_bytes;  /* device bytes the fit server may hold for requests (default 256 MiB) */
+  int32_t iters_per_tick;    /* LM iterations per server launch (default 10) */
+  int32_t fit_iters;         /* LM iterations per fit (default 50) */
+  double lm_lambda0;         /* initial Marquardt damping (default 1e-3) */
+} sb_config;
+
+void sb_config_default(sb_config *cfg);
+
+/* Create a context on HIP device `device`: validates and uploads the surfaces
+ * (as interleaved (M0, M1) float pairs, wavelength-major), prepares the band
+ * registry.  cfg may be NULL for defaults.  On success *out owns device memory
+ * until sb_destroy. */
+sb_status sb_create(const sb_model_desc *model, const sb_config *cfg, int device, sb_ctx **out);
+
+/* Stop the fit server (pending fits become SB_CANCELLED), free everything.
+ * The caller must have finished all work it queued with this context. */
+sb_status sb_destroy(sb_ctx *ctx);
+
+/* Register a bandpass (the paper's bandpass registration): n >= 2 samples of
+ * (wave [Angstrom, strictly increasing], trans >= 0), host arrays, copied.
+ * Builds its trapezoid grid (at most SB_MAX_BAND_POINTS nodes) and stores
+ * lam_k and W_k = w_k lam_k T(lam_k)/(h c) in float32 on the device.
+ * Synchronous.  Not allowed while compute calls of this context are in
+ * flight.  *band_id receives 0, 1, 2, ... in registration order. */
+sb_status sb_add_band(sb_ctx *ctx, const double *wave, const double *trans, int32_t n, int32_t *band_id);
+
+/* Host-only helper (no context, no GPU): the quadrature grid sb_add_band builds.
+ * Writes at most cap nodes to lam_out/weight_out (float32, weight = W_k above);
+ * *n_points receives the node count.  SB_ERR_ARG if it exceeds cap. */
+sb_status sb_band_grid(const double *wave, const double *trans, int32_t n, double max_spacing,
+                       int32_t cap, float *lam_out, float *weight_out, int32_t *n_points);
+
+/* Batch flags. */
+enum {
+  SB_OBS_BROADCAST = 1,  /* one observation table [n_obs] shared by all n_sn parameter samples */
+  SB_OUT_CHI2 = 2        /* sb_bandflux: write chi2 per supernova instead of fluxes;
+                            sb_bandflux_vjp: cotangent = d chi2 / d f = 2 (f - data) inv_sigma2 */
+};
+
+/* A batch of supernovae in structure-of-arrays layout, all device pointers.
+ * Supernova s has parameters z[s], t0[s], x0[s], x1[s], c[s] (z > -1).
+ * Without SB_OBS_BROADCAST its observations are i in [sn_offsets[s], sn_offsets[s+1])
+ * (CSR, non-decreasing, sn_offsets[0] = 0, sn_offsets[n_sn] = n_obs), at time t[i]
+ * (days, same origin as t0) through band band[i].  With SB_OBS_BROADCAST,
+ * sn_offsets is ignored and every sample sees all n_obs observations.
+ * data / inv_sigma2 ([n_obs]) are read only with SB_OUT_CHI2. */
+typedef struct {
+  int32_t n_sn, n_obs, flags;
+  const float *z, *t0, *x0, *x1, *c;
+  const float *t;
+  const int32_t *band;
+  const int32_t *sn_offsets;
+  const float *data, *inv_sigma2;
+} sb_batch;
+
+/* Bandflux of every observation (the bandflux equation).
+ * out: [n_obs] fluxes; with SB_OBS_BROADCAST [n_sn][n_obs]; with SB_OUT_CHI2
+ * [n_sn] chi2_s = sum_i (f_i - data_i)^2 inv_sigma2_i.  One workgroup per
+ * supernova, or, with SB_OBS_BROADCAST, a persistent grid that takes samples
+ * from a work counter and keeps the observation table in LDS. */
+sb_status sb_bandflux(sb_ctx *ctx, const sb_batch *batch, float *out, void *hip_stream);
+
+/* Forward pass plus adjoint: grad[s*5 + q] = sum_i gbar_i d f_i / d theta_s[q],
+ * theta = (z, t0, x0, x1, c), where gbar_i = cotangent[i], or with SB_OUT_CHI2
+ * gbar_i = 2 (f_i - data_i) inv_sigma2_i (cotangent must then be NULL).
+ * grad is required ([n_sn*5]); flux_out ([n_obs], or [n_sn][n_obs] with
+ * broadcast), jac_out ([n_obs][5], or [n_sn][n_obs][5]) and chi2_out ([n_sn],
+ * SB_OUT_CHI2 only) may be NULL.  Each supernova's sums are reduced in a fixed
+ * order by one workgroup: results are bitwise reproducible. */
+sb_status sb_bandflux_vjp(sb_ctx *ctx, const sb_batch *batch, const float *cotangent, float *grad,
+                          float *flux_out, float *jac_out, float *chi2_out, void *hip_stream);
+
+/* Wait for the context's work on hip_stream and report the sticky device
+ * flags (SB_ERR_RANGE if any result was turned into NaN since the last call);
+ * clears them.  Synchronises hip_stream. */
+sb_status sb_device_check(sb_ctx *ctx, void *hip_stream);
+
+/* ---------------------------------------------------------------- fit server
+ * Continuous batching of light-curve fits (the paper's optimisation example):
+ * each request is one supernova with z given and (t0, x0, x1, c) free, fitted by
+ * cfg.fit_iters Levenberg-Marquardt damped Gauss-Newton iterations on
+ * (t0, ln x0, x1, c) with weights 1/sigma^2, lambda0 = cfg.lm_lambda0, x10 on a
+ * rejected step and /10 on an accepted one, lambda kept in [1e-9, 1e9].
+ * A server thread admits queued requests while device slots and the byte budget
+ * allow, runs cfg.iters_per_tick iterations of every resident fit per launch,
+ * and retires finished fits; requests that arrive while others run join the next
+ * launch.  Per-supernova state stays on the device between launches.  A fit's
+ * result does not depend on which other fits share its launches. */
+typedef struct {
+  int32_t n_obs;             /* 1..cfg.max_obs_per_fit */
+  const float *t;            /* host [n_obs], copied at submit */
+  const int32_t *band;       /* host [n_obs] */
+  const float *data, *sigma; /* host [n_obs], sigma > 0 */
+  float z;                   /* fixed */
+  float t0, x0, x1, c;       /* starting point, x0 > 0 */
+} sb_fit_request;
+
+typedef struct {
+  sb_status status;          /* SB_OK, SB_PENDING, SB_CANCELLED, SB_FIT_DIVERGED */
+  float z, t0, x0, x1, c;    /* fitted parameters (z as given) */
+  float chi2;                /* at the fitted parameters */
+  int32_t iters;             /* LM iterations run */
+  int32_t n_accept;          /* accepted steps */
+  double t_submit, t_admit, t_done;  /* host monotonic clock, seconds */
+} sb_fit_result;
+
+/* Queue a request; never waits for the GPU.  SB_ERR_ARG for a malformed request
+ * (sizes, band ids, non-finite values), SB_ERR_BUDGET if it alone exceeds the
+ * byte budget.  *ticket identifies the result. */
+sb_status sb_fit_submit(sb_ctx *ctx, const sb_fit_request *req, uint64_t *ticket);
+
+/* SB_PENDING while the fit runs; otherwise fills *out, forgets the ticket and
+ * returns SB_OK (out->status carries the fit's own status). */
+sb_status sb_fit_poll(sb_ctx *ctx, uint64_t ticket, sb_fit_result *out);
+
+/* Like sb_fit_poll but blocks up to timeout_s seconds (SB_PENDING on timeout). */
+sb_status sb_fit_wait(sb_ctx *ctx, uint64_t ticket, double timeout_s, sb_fit_result *out);
+
+/* Cancel a queued or running fit; its result becomes SB_CANCELLED. */
+sb_status sb_fit_cancel(sb_ctx *ctx, uint64_t ticket);
+
+typedef struct {
+  int64_t submitted, admitted, completed, cancelled, rejected;
+  int64_t ticks;               /* server launches */
+  int32_t queue_depth;         /* waiting for admission */
+  int32_t active_slots;        /* resident on the device */
+  int64_t bytes_in_use, budget_bytes;
+  double busy_seconds;         /* host time with at least one fit resident */
+} sb_stats_t;
+
+sb_status sb_stats(sb_ctx *ctx, sb_stats_t *out);
+
+const char *sb_status_string(sb_status st);
+const char *sb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SALTBF_H */

@@ -1,0 +1,268 @@
+// Bandflux, adjoint and sweep kernels (gfx950).
+//
+// One 256-thread workgroup evaluates one supernova (or one parameter sample of
+// a sweep): it scans the supernova's observations for the bands they use and
+// the surface rows their phases touch, then per band builds the wavelength
+// weight vectors and row projections (sb_device.h) and finishes every
+// observation of that band with a 4-tap phase interpolation.  The adjoint
+// accumulates sum_i gbar_i d f_i / d theta per thread and reduces it over the
+// workgroup in a fixed order, so one writer produces each supernova's
+// gradient without atomics.
+#include <climits>
+
+#include "sb_device.h"
+
+namespace sbk {
+
+struct SnShared {
+  unsigned mask[2];
+  int rlo[SB_MAX_BANDS];
+  int rhi[SB_MAX_BANDS];
+  int flag;
+  int item;
+  float red[NWAVES * 8];
+};
+
+// Per-observation outputs of an observation that cannot be evaluated.
+template <int MODE>
+__device__ inline void write_obs(const KBatch& b, size_t o, float f, const float* d) {
+  if (MODE == FWD) {
+    if (!(b.flags & SB_OUT_CHI2)) b.flux[o] = f;
+  } else {
+    if (b.flux) b.flux[o] = f;
+    if (b.jac) {
+#pragma unroll
+      for (int q = 0; q < SB_N_PARAMS; ++q) b.jac[o * SB_N_PARAMS + q] = d[q];
+    }
+  }
+}
+
+// Evaluate supernova (or sample) `sn`.  All threads of the workgroup call it.
+template <int MODE, bool BCAST>
+__device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int sn, const Lds& L,
+                        SnShared& S) {
+  const int tid = threadIdx.x;
+  const bool chi2 = (b.flags & SB_OUT_CHI2) != 0;
+  const float z = b.z[sn], t0 = b.t0[sn], x0 = b.x0[sn], x1 = b.x1[sn], c = b.c[sn];
+  const float s = 1.0f / (1.0f + z);
+  const float A = x0 * s;
+  const float qnan = __builtin_nanf("");
+
+  int lo = 0, hi = b.n_obs;
+  bool csr_bad = false;
+  if (!BCAST) {
+    lo = b.off[sn];
+    hi = b.off[sn + 1];
+    if (lo < 0 || hi < lo || hi > b.n_obs) {
+      csr_bad = true;
+      lo = hi = 0;
+    }
+  }
+  const size_t obase = BCAST ? (size_t)sn * (size_t)b.n_obs : 0;
+
+  if (tid < SB_MAX_BANDS) {
+    S.rlo[tid] = INT_MAX;
+    S.rhi[tid] = -1;
+  }
+  if (tid < 2) S.mask[tid] = 0u;
+  __syncthreads();
+
+  // acc: gradient (z, t0, x0, x1, c) and chi2
+  float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (csr_bad) {
+    if (tid == 0) atomicOr(b.err, EFLAG_CSR);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc[q] = qnan;
+  }
+
+  // scan: bands in use, rows touched; observations with nothing to integrate
+  for (int i = lo + tid; i < hi; i += WG) {
+    const int bd = b.band[i];
+    const PhaseCell pc = phase_cell(b.t[i], t0, s, m);
+    const bool bad_band = (unsigned)bd >= (unsigned)m.n_bands;
+    if (bad_band || pc.nan) {
+      if (bad_band) atomicOr(b.err, EFLAG_BAND);
+      const float dn[5] = {qnan, qnan, qnan, qnan, qnan};
+      write_obs<MODE>(b, obase + i, qnan, dn);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) acc[q] = qnan;
+      continue;
+    }
+    if (!pc.in) {
+      const float d0[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+      write_obs<MODE>(b, obase + i, 0.f, d0);
+      if (chi2) {
+        const float r = -b.data[i];
+        acc[5] = fmaf(r * r, b.w[i], acc[5]);
+      }
+      continue;
+    }
+    atomicMin(&S.rlo[bd], pc.r0);
+    atomicMax(&S.rhi[bd], pc.r1);
+    atomicOr(&S.mask[bd >> 5], 1u << (bd & 31));
+  }
+  __syncthreads();
+
+  const unsigned masks[2] = {S.mask[0], S.mask[1]};
+  for (int h = 0; h < 2; ++h) {
+    unsigned msk = masks[h];
+    while (msk) {
+      const int bd = h * 32 + __ffs(msk) - 1;
+      msk &= msk - 1;
+      const int rlo = S.rlo[bd], rhi = S.rhi[bd];
+      const bool ok = band_rows<MODE>(m, tb, bd, s, c, x1, rlo, rhi, L, &S.flag);
+      if (!ok && tid == 0) atomicOr(b.err, EFLAG_WINDOW);
+      constexpr int NR = ModeInfo<MODE>::NR;
+      for (int i = lo + tid; i < hi; i += WG) {
+        if (b.band[i] != bd) continue;
+        const PhaseCell pc = phase_cell(b.t[i], t0, s, m);
+        if (!pc.in) continue;
+        float f, dv[5];
+        if (!ok) {
+          f = qnan;
+#pragma unroll
+          for (int q = 0; q < 5; ++q) dv[q] = qnan;
+        } else {
+          float wp[4];
+          cr_weights(pc.x, pc.edge, wp);
+          const int tb0 = pc.edge ? 1 : 0, tb1 = pc.edge ? 3 : 4;
+          float Sx = 0.f;
+          if (MODE == FWD) {
+            for (int t = tb0; t < tb1; ++t) Sx = fmaf(wp[t], L.R[row_index(pc.a - 1 + t, rlo, rhi) * NR], Sx);
+            f = A * Sx;
+          } else {
+            float dw[4];
+            cr_dweights(pc.x, pc.edge, dw);
+            float S1 = 0.f, Sc = 0.f, Sl = 0.f, Sp = 0.f;
+            for (int t = tb0; t < tb1; ++t) {
+              const float* r = L.R + row_index(pc.a - 1 + t, rlo, rhi) * NR;
+              Sx = fmaf(wp[t], r[0], Sx);
+              Sp = fmaf(dw[t], r[0], Sp);
+              S1 = fmaf(wp[t], r[1], S1);
+              Sc = fmaf(wp[t], r[2], Sc);
+              if (MODE == VJP) Sl = fmaf(wp[t], r[3], Sl);
+            }
+            Sp *= m.inv_dphase;
+            f = A * Sx;
+            const float As = A * s;
+            dv[0] = -s * f - As * fmaf(pc.p, Sp, Sl);   // z
+            dv[1] = -As * Sp;                           // t0
+            dv[2] = s * Sx;                             // x0
+            dv[3] = A * S1;                             // x1
+            dv[4] = A * Sc;                             // c
+          }
+        }
+        if (MODE == FWD) {
+          if (chi2) {
+            const float r = f - b.data[i];
+            acc[5] = fmaf(r * r, b.w[i], acc[5]);
+          } else {
+            b.flux[obase + i] = f;
+          }
+        } else {
+          write_obs<MODE>(b, obase + i, f, dv);
+          float gbar;
+          if (chi2) {
+            const float r = f - b.data[i];
+            const float wi = b.w[i];
+            acc[5] = fmaf(r * r, wi, acc[5]);
+            gbar = 2.f * r * wi;
+          } else {
+            gbar = b.cot[obase + i];
+          }
+#pragma unroll
+          for (int q = 0; q < 5; ++q) acc[q] = fmaf(gbar, dv[q], acc[q]);
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  if (MODE == VJP) {
+    block_sum<6>(acc, S.red);
+    if (tid == 0) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) b.grad[(size_t)sn * SB_N_PARAMS + q] = acc[q];
+      if (chi2 && b.chi2) b.chi2[sn] = acc[5];
+    }
+  } else if (chi2) {
+    float a1[1] = {acc[5]};
+    block_sum<1>(a1, S.red);
+    if (tid == 0) b.chi2[sn] = a1[0];
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(WG) void k_sn(KModel m, KTables tb, KBatch b) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ SnShared S;
+  const Lds L = lds_carve<MODE>(smem, m, tb.max_pts);
+  sn_body<MODE, false>(m, tb, b, blockIdx.x, L, S);
+}
+
+// Persistent sweep: a fixed grid takes samples from a work counter until all
+// are done; every sample sees the whole observation table.
+template <int MODE>
+__global__ __launch_bounds__(WG) void k_sweep(KModel m, KTables tb, KBatch b) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ SnShared S;
+  const Lds L = lds_carve<MODE>(smem, m, tb.max_pts);
+  for (;;) {
+    if (threadIdx.x == 0) S.item = atomicAdd(b.counter, 1);
+    __syncthreads();
+    const int item = S.item;
+    __syncthreads();
+    if (item >= b.n_sn) break;
+    sn_body<MODE, true>(m, tb, b, item, L, S);
+  }
+}
+
+size_t lds_bytes(const KModel& m, int max_pts, bool adj) {
+  return adj ? lds_layout_bytes<VJP>(m.n_phase, m.n_wave, max_pts)
+             : lds_layout_bytes<FWD>(m.n_phase, m.n_wave, max_pts);
+}
+
+template <typename K>
+static hipError_t prep_lds(K kern, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_sn(bool adj, const KModel& m, const KTables& tb, const KBatch& b, hipStream_t st) {
+  const size_t lds = lds_bytes(m, tb.max_pts, adj);
+  hipError_t e;
+  if (adj) {
+    if ((e = prep_lds(k_sn<VJP>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sn<VJP>, dim3(b.n_sn), dim3(WG), lds, st, m, tb, b);
+  } else {
+    if ((e = prep_lds(k_sn<FWD>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sn<FWD>, dim3(b.n_sn), dim3(WG), lds, st, m, tb, b);
+  }
+  return hipGetLastError();
+}
+
+int sweep_blocks_per_cu(bool adj, const KModel& m, int max_pts) {
+  const size_t lds = lds_bytes(m, max_pts, adj);
+  int nb = 0;
+  hipError_t e = adj ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep<VJP>, WG, lds)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep<FWD>, WG, lds);
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+hipError_t launch_sweep(bool adj, const KModel& m, const KTables& tb, const KBatch& b, int grid,
+                        hipStream_t st) {
+  const size_t lds = lds_bytes(m, tb.max_pts, adj);
+  hipError_t e = hipMemsetAsync(b.counter, 0, sizeof(int), st);
+  if (e != hipSuccess) return e;
+  if (adj) {
+    if ((e = prep_lds(k_sweep<VJP>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sweep<VJP>, dim3(grid), dim3(WG), lds, st, m, tb, b);
+  } else {
+    if ((e = prep_lds(k_sweep<FWD>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sweep<FWD>, dim3(grid), dim3(WG), lds, st, m, tb, b);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sbk

@@ -1,0 +1,54 @@
+// Context object and host helpers shared by sb_host.cpp and sb_server.cpp.
+#pragma once
+
+#include <atomic>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sb_internal.h"
+
+namespace sbh {
+
+class Server;
+
+sb_status set_error(sb_status st, const std::string& msg);
+double now_seconds();
+
+// Quadrature grid of one band, float64: nodes, and W_k = w_k lam_k T_k / (hc).
+sb_status build_band_grid(const double* wave, const double* trans, int n, double spacing,
+                          std::vector<double>& lam, std::vector<double>& W);
+
+}  // namespace sbh
+
+struct sb_ctx {
+  int device = 0;
+  sb_config cfg{};
+  sbk::KModel km{};
+  double wave_lo = 0, wave_hi = 0;     // surface wavelength range (Angstrom)
+  float2* d_surf = nullptr;
+  float2* d_pts = nullptr;
+  int* d_npts = nullptr;
+  int* d_err = nullptr;
+  int* d_counters = nullptr;           // ring of sweep work counters
+  std::atomic<unsigned> next_counter{0};
+  int n_bands = 0;
+  int max_pts = 0;
+  std::vector<double> band_lo, band_hi; // sample range of each band
+  int n_cu = 1;
+  int sweep_bpc[2] = {0, 0};           // persistent blocks per CU (fwd, adj), 0 = not queried
+  size_t max_lds = 65536;
+  std::mutex mu;                       // band registration, server start
+  sbh::Server* server = nullptr;
+
+  sbk::KTables tables() const {
+    sbk::KTables t;
+    t.surf = d_surf;
+    t.pts = d_pts;
+    t.npts = d_npts;
+    t.max_pts = max_pts;
+    return t;
+  }
+};
+
+constexpr int SB_N_COUNTERS = 256;

@@ -1,0 +1,323 @@
+// Fit-step kernel of the serving loop (gfx950).
+//
+// One 256-thread workgroup advances one resident fit by up to `iters`
+// Levenberg-Marquardt iterations.  Each evaluation runs the bandflux pipeline of
+// sb_device.h in FIT mode (row projections for the flux, d/dx1 and d/dc; d/dt0
+// comes from the phase-weight derivatives and d/d ln x0 equals the flux), and
+// accumulates chi2, J^T W J and J^T W r over the fit's observations with a
+// fixed-order workgroup reduction.  Thread 0 does the 4x4 damped solve.  The
+// fit's state is read from and written back to its slot, so a fit gives the
+// same result however its iterations are split over launches and whichever
+// other fits share the launch.
+#include <climits>
+
+#include "sb_device.h"
+
+namespace sbk {
+
+struct FitShared {
+  unsigned mask[2];
+  int rlo[SB_MAX_BANDS];
+  int rhi[SB_MAX_BANDS];
+  int flag;
+  int skip;
+  float red[NWAVES * 16];
+  float q[4], qt[4];
+  float lambda, chi2;
+  float H[10], g[4];
+  int iter, n_accept, status;
+};
+
+// chi2, H (packed) and g at parameters q = (t0, ln x0, x1, c); valid in thread 0.
+struct FitObs {
+  const float* t;
+  const int* band;
+  const float* data;
+  const float* w;
+  int n;
+};
+
+__device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, const FitObs& O, float s,
+                         const float* q, const Lds& L, FitShared& S, float (&out)[15]) {
+  const int tid = threadIdx.x;
+  const float t0 = q[0], x0 = expf(q[1]), x1 = q[2], c = q[3];
+  const float A = x0 * s;
+  if (tid < SB_MAX_BANDS) {
+    S.rlo[tid] = INT_MAX;
+    S.rhi[tid] = -1;
+  }
+  if (tid < 2) S.mask[tid] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 15; ++k) out[k] = 0.f;
+  for (int i = tid; i < O.n; i += WG) {
+    const int bd = O.band[i];
+    const PhaseCell pc = phase_cell(O.t[i], t0, s, m);
+    if (!pc.in || pc.nan || (unsigned)bd >= (unsigned)m.n_bands) {
+      const float r = O.data[i];
+      out[14] = fmaf(r * r, O.w[i], out[14]);
+      continue;
+    }
+    atomicMin(&S.rlo[bd], pc.r0);
+    atomicMax(&S.rhi[bd], pc.r1);
+    atomicOr(&S.mask[bd >> 5], 1u << (bd & 31));
+  }
+  __syncthreads();
+  const unsigned masks[2] = {S.mask[0], S.mask[1]};
+  constexpr int NR = ModeInfo<FIT>::NR;
+  for (int h = 0; h < 2; ++h) {
+    unsigned msk = masks[h];
+    while (msk) {
+      const int bd = h * 32 + __ffs(msk) - 1;
+      msk &= msk - 1;
+      const int rlo = S.rlo[bd], rhi = S.rhi[bd];
+      const bool ok = band_rows<FIT>(m, tb, bd, s, c, x1, rlo, rhi, L, &S.flag);
+      if (!ok && tid == 0) atomicOr(F.err, EFLAG_WINDOW);
+      for (int i = tid; i < O.n; i += WG) {
+        if (O.band[i] != bd) continue;
+        const PhaseCell pc = phase_cell(O.t[i], t0, s, m);
+        if (!pc.in || pc.nan) continue;
+        float J[4], f;
+        if (!ok) {
+          f = __builtin_nanf("");
+          J[0] = J[1] = J[2] = J[3] = f;
+        } else {
+          float wp[4], dw[4];
+          cr_weights(pc.x, pc.edge, wp);
+          cr_dweights(pc.x, pc.edge, dw);
+          const int tb0 = pc.edge ? 1 : 0, tb1 = pc.edge ? 3 : 4;
+          float Sx = 0.f, Sp = 0.f, S1 = 0.f, Sc = 0.f;
+          for (int t = tb0; t < tb1; ++t) {
+            const float* r = L.R + row_index(pc.a - 1 + t, rlo, rhi) * NR;
+            Sx = fmaf(wp[t], r[0], Sx);
+            Sp = fmaf(dw[t], r[0], Sp);
+            S1 = fmaf(wp[t], r[1], S1);
+            Sc = fmaf(wp[t], r[2], Sc);
+          }
+          f = A * Sx;
+          J[0] = -A * s * Sp * m.inv_dphase;   // d/dt0
+          J[1] = f;                            // d/d ln x0
+          J[2] = A * S1;                       // d/dx1
+          J[3] = A * Sc;                       // d/dc
+        }
+        const float wi = O.w[i];
+        const float r = O.data[i] - f;
+        int k = 0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const float wa = wi * J[a];
+#pragma unroll
+          for (int bb = a; bb < 4; ++bb) {
+            out[k] = fmaf(wa, J[bb], out[k]);
+            ++k;
+          }
+          out[10 + a] = fmaf(wa, r, out[10 + a]);
+        }
+        out[14] = fmaf(r * r, wi, out[14]);
+      }
+      __syncthreads();
+    }
+  }
+  block_sum<15>(out, S.red);
+}
+
+// Solve (H + lambda diag H) d = g by Cholesky (thread 0).  False if a pivot is
+// not positive.
+__device__ bool damped_solve(const float* H, const float* g, float lambda, float* d) {
+  float a[4][4];
+  int k = 0;
+  for (int i = 0; i < 4; ++i)
+    for (int j = i; j < 4; ++j) {
+      a[i][j] = H[k];
+      a[j][i] = H[k];
+      ++k;
+    }
+  for (int i = 0; i < 4; ++i) a[i][i] = fmaf(lambda, a[i][i], a[i][i]);
+  float l[4][4] = {};
+  for (int i = 0; i < 4; ++i) {
+    for (int j = 0; j <= i; ++j) {
+      float sum = a[i][j];
+      for (int p = 0; p < j; ++p) sum -= l[i][p] * l[j][p];
+      if (i == j) {
+        if (!(sum > 0.f) || !isfinite(sum)) return false;
+        l[i][i] = sqrtf(sum);
+      } else {
+        l[i][j] = sum / l[j][j];
+      }
+    }
+  }
+  float y[4];
+  for (int i = 0; i < 4; ++i) {
+    float sum = g[i];
+    for (int p = 0; p < i; ++p) sum -= l[i][p] * y[p];
+    y[i] = sum / l[i][i];
+  }
+  for (int i = 3; i >= 0; --i) {
+    float sum = y[i];
+    for (int p = i + 1; p < 4; ++p) sum -= l[p][i] * d[p];
+    d[i] = sum / l[i][i];
+  }
+  for (int i = 0; i < 4; ++i)
+    if (!isfinite(d[i])) return false;
+  return true;
+}
+
+__global__ __launch_bounds__(WG) void k_fit(KModel m, KTables tb, KFit F) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ FitShared S;
+  const Lds L = lds_carve<FIT>(smem, m, tb.max_pts);
+  const int tid = threadIdx.x;
+  FitSlot* sl = F.slots + F.active[blockIdx.x];
+  const int adm = F.admit[blockIdx.x];
+  FitObs O;
+  float z;
+  if (adm >= 0) {
+    // first launch of this fit: move its observations from the inbox to the arena
+    const AdmitHeader h = F.hdr[adm];
+    for (int i = tid; i < h.n_obs; i += WG) {
+      F.t[h.arena_off + i] = F.in_t[h.src_off + i];
+      F.band[h.arena_off + i] = F.in_band[h.src_off + i];
+      F.data[h.arena_off + i] = F.in_data[h.src_off + i];
+      F.w[h.arena_off + i] = F.in_w[h.src_off + i];
+    }
+    if (tid == 0) {
+      sl->obs_off = h.arena_off;
+      sl->n_obs = h.n_obs;
+      sl->iter = -1;
+      sl->n_accept = 0;
+      sl->status = SB_OK;
+      sl->z = h.z;
+      sl->q[0] = h.t0;
+      sl->q[1] = h.lnx0;
+      sl->q[2] = h.x1;
+      sl->q[3] = h.c;
+      sl->lambda = F.lambda0;
+      sl->chi2 = 0.f;
+      for (int k = 0; k < 10; ++k) sl->H[k] = 0.f;
+      for (int k = 0; k < 4; ++k) sl->g[k] = 0.f;
+    }
+    // this launch reads the inbox copy; the arena copy serves the later launches
+    O.t = F.in_t + h.src_off;
+    O.band = F.in_band + h.src_off;
+    O.data = F.in_data + h.src_off;
+    O.w = F.in_w + h.src_off;
+    O.n = h.n_obs;
+    z = h.z;
+  } else {
+    O.t = F.t + sl->obs_off;
+    O.band = F.band + sl->obs_off;
+    O.data = F.data + sl->obs_off;
+    O.w = F.w + sl->obs_off;
+    O.n = sl->n_obs;
+    z = sl->z;
+  }
+  const float s = 1.0f / (1.0f + z);
+  if (tid == 0 && adm >= 0) {
+    const AdmitHeader h = F.hdr[adm];
+    S.q[0] = h.t0;
+    S.q[1] = h.lnx0;
+    S.q[2] = h.x1;
+    S.q[3] = h.c;
+    for (int k = 0; k < 10; ++k) S.H[k] = 0.f;
+    for (int k = 0; k < 4; ++k) S.g[k] = 0.f;
+    S.lambda = F.lambda0;
+    S.chi2 = 0.f;
+    S.iter = -1;
+    S.n_accept = 0;
+    S.status = SB_OK;
+  } else if (tid == 0) {
+    for (int k = 0; k < 4; ++k) S.q[k] = sl->q[k];
+    for (int k = 0; k < 10; ++k) S.H[k] = sl->H[k];
+    for (int k = 0; k < 4; ++k) S.g[k] = sl->g[k];
+    S.lambda = sl->lambda;
+    S.chi2 = sl->chi2;
+    S.iter = sl->iter;
+    S.n_accept = sl->n_accept;
+    S.status = sl->status;
+  }
+  __syncthreads();
+  float out[15];
+  const bool first = S.iter < 0;
+  __syncthreads();
+  if (first) {
+    fit_eval(m, tb, F, O, s, S.q, L, S, out);
+    if (tid == 0) {
+      if (isfinite(out[14])) {
+        for (int k = 0; k < 10; ++k) S.H[k] = out[k];
+        for (int k = 0; k < 4; ++k) S.g[k] = out[10 + k];
+        S.chi2 = out[14];
+        S.iter = 0;
+        S.lambda = F.lambda0;
+      } else {
+        S.chi2 = out[14];
+        S.status = SB_FIT_DIVERGED;
+      }
+    }
+    __syncthreads();
+  }
+  for (int it = 0; it < F.iters; ++it) {
+    // every thread reads the loop state before thread 0 may change it
+    const bool done = (S.status != SB_OK) || (S.iter >= F.fit_iters);
+    __syncthreads();
+    if (done) break;
+    if (tid == 0) {
+      float d[4];
+      if (damped_solve(S.H, S.g, S.lambda, d)) {
+        for (int k = 0; k < 4; ++k) S.qt[k] = S.q[k] + d[k];
+        S.skip = 0;
+      } else {
+        S.lambda = fminf(S.lambda * 10.f, 1e9f);
+        S.iter += 1;
+        S.skip = 1;
+      }
+    }
+    __syncthreads();
+    const int skip = S.skip;
+    __syncthreads();
+    if (skip) continue;
+    fit_eval(m, tb, F, O, s, S.qt, L, S, out);
+    if (tid == 0) {
+      if (isfinite(out[14]) && out[14] < S.chi2) {
+        for (int k = 0; k < 4; ++k) S.q[k] = S.qt[k];
+        for (int k = 0; k < 10; ++k) S.H[k] = out[k];
+        for (int k = 0; k < 4; ++k) S.g[k] = out[10 + k];
+        S.chi2 = out[14];
+        S.lambda = fmaxf(S.lambda * 0.1f, 1e-9f);
+        S.n_accept += 1;
+      } else {
+        S.lambda = fminf(S.lambda * 10.f, 1e9f);
+      }
+      S.iter += 1;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    for (int k = 0; k < 4; ++k) sl->q[k] = S.q[k];
+    for (int k = 0; k < 10; ++k) sl->H[k] = S.H[k];
+    for (int k = 0; k < 4; ++k) sl->g[k] = S.g[k];
+    sl->lambda = S.lambda;
+    sl->chi2 = S.chi2;
+    sl->iter = S.iter;
+    sl->n_accept = S.n_accept;
+    sl->status = S.status;
+    const int oi = F.out_idx[blockIdx.x];
+    if (oi >= 0) F.results[oi] = *sl;
+  }
+}
+
+size_t fit_lds_bytes(const KModel& m, int max_pts) {
+  return lds_layout_bytes<FIT>(m.n_phase, m.n_wave, max_pts);
+}
+
+hipError_t launch_fit(const KModel& m, const KTables& tb, const KFit& f, hipStream_t st) {
+  if (f.n_active <= 0) return hipSuccess;
+  const size_t lds = fit_lds_bytes(m, tb.max_pts);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_fit, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_fit, dim3(f.n_active), dim3(WG), lds, st, m, tb, f);
+  return hipGetLastError();
+}
+
+}  // namespace sbk

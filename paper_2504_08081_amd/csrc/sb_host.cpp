@@ -1,0 +1,367 @@
+// Host side of the C ABI: context, surfaces, band registry, launch of the
+// bandflux / adjoint / sweep kernels, device error flags.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "sb_ctx.h"
+#include "sb_server.h"
+
+namespace {
+thread_local std::string g_last_error;
+
+// h c with the exact SI values of h (erg s) and c (Angstrom / s): erg Angstrom.
+constexpr double HC_ERG_ANGSTROM = 6.62607015e-27 * 2.99792458e18;
+
+bool finite_all(const double* a, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+sb_status hip_fail(hipError_t e, const char* what) {
+  return sbh::set_error(SB_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+}  // namespace
+
+namespace sbh {
+
+sb_status set_error(sb_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+double now_seconds() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+sb_status build_band_grid(const double* wave, const double* trans, int n, double spacing,
+                          std::vector<double>& lam, std::vector<double>& W) {
+  if (!wave || !trans || n < 2) return set_error(SB_ERR_ARG, "band: need at least 2 samples");
+  if (!(spacing > 0.0) || !std::isfinite(spacing)) return set_error(SB_ERR_ARG, "band: spacing must be > 0");
+  if (!finite_all(wave, n) || !finite_all(trans, n)) return set_error(SB_ERR_ARG, "band: non-finite sample");
+  for (int i = 0; i < n; ++i) {
+    if (i > 0 && !(wave[i] > wave[i - 1])) return set_error(SB_ERR_ARG, "band: wavelengths must increase");
+    if (trans[i] < 0.0) return set_error(SB_ERR_ARG, "band: negative transmission");
+  }
+  const double L = wave[0], U = wave[n - 1];
+  // N equal intervals no wider than the spacing (tolerant to rounding of an exact ratio)
+  const double ratio = (U - L) / spacing;
+  if (ratio > 1e7) return set_error(SB_ERR_ARG, "band: too many quadrature nodes");
+  long N = (long)std::ceil(ratio - 1e-9);
+  if (N < 1) N = 1;
+  if (N + 1 > SB_MAX_BAND_POINTS) return set_error(SB_ERR_ARG, "band: more than SB_MAX_BAND_POINTS nodes");
+  const double delta = (U - L) / (double)N;
+  lam.assign(N + 1, 0.0);
+  W.assign(N + 1, 0.0);
+  int seg = 0;
+  for (long k = 0; k <= N; ++k) {
+    const double x = (k == N) ? U : L + delta * (double)k;
+    while (seg < n - 2 && x > wave[seg + 1]) ++seg;
+    // linear interpolation of the transmission between samples seg and seg+1
+    const double slope = (trans[seg + 1] - trans[seg]) / (wave[seg + 1] - wave[seg]);
+    const double T = slope * (x - wave[seg]) + trans[seg];
+    const double w = (k == 0 || k == N) ? 0.5 * delta : delta;
+    lam[k] = x;
+    W[k] = w * x * T / HC_ERG_ANGSTROM;
+  }
+  return SB_OK;
+}
+
+}  // namespace sbh
+
+using sbh::set_error;
+
+extern "C" {
+
+const char* sb_last_error(void) { return g_last_error.c_str(); }
+
+const char* sb_status_string(sb_status st) {
+  switch (st) {
+    case SB_OK: return "ok";
+    case SB_PENDING: return "pending";
+    case SB_CANCELLED: return "cancelled";
+    case SB_FIT_DIVERGED: return "fit diverged";
+    case SB_ERR_ARG: return "invalid argument";
+    case SB_ERR_RANGE: return "out of range (band window, band id or CSR offsets)";
+    case SB_ERR_DEVICE: return "device error";
+    case SB_ERR_NOMEM: return "out of memory";
+    case SB_ERR_BUDGET: return "request exceeds the serving budget";
+    case SB_ERR_STATE: return "invalid state";
+    case SB_ERR_NOTFOUND: return "unknown ticket";
+    default: return "unknown status";
+  }
+}
+
+void sb_config_default(sb_config* cfg) {
+  if (!cfg) return;
+  cfg->max_spacing = 5.0;
+  cfg->max_obs_per_fit = 256;
+  cfg->max_slots = 1024;
+  cfg->hbm_budget_bytes = 256ll << 20;
+  cfg->iters_per_tick = 10;
+  cfg->fit_iters = 50;
+  cfg->lm_lambda0 = 1e-3;
+}
+
+sb_status sb_band_grid(const double* wave, const double* trans, int32_t n, double max_spacing, int32_t cap,
+                       float* lam_out, float* weight_out, int32_t* n_points) {
+  if (!n_points) return set_error(SB_ERR_ARG, "sb_band_grid: n_points is NULL");
+  std::vector<double> lam, W;
+  sb_status st = sbh::build_band_grid(wave, trans, n, max_spacing, lam, W);
+  if (st != SB_OK) return st;
+  *n_points = (int32_t)lam.size();
+  if ((int)lam.size() > cap) return set_error(SB_ERR_ARG, "sb_band_grid: cap too small");
+  for (size_t k = 0; k < lam.size(); ++k) {
+    if (lam_out) lam_out[k] = (float)lam[k];
+    if (weight_out) weight_out[k] = (float)W[k];
+  }
+  return SB_OK;
+}
+
+static void free_ctx(sb_ctx* c) {
+  if (!c) return;
+  if (c->d_surf) (void)hipFree(c->d_surf);
+  if (c->d_pts) (void)hipFree(c->d_pts);
+  if (c->d_npts) (void)hipFree(c->d_npts);
+  if (c->d_err) (void)hipFree(c->d_err);
+  if (c->d_counters) (void)hipFree(c->d_counters);
+  delete c;
+}
+
+sb_status sb_create(const sb_model_desc* md, const sb_config* cfg_in, int device, sb_ctx** out) {
+  if (!md || !out) return set_error(SB_ERR_ARG, "sb_create: NULL argument");
+  *out = nullptr;
+  if (md->n_phase < 4 || md->n_phase > sbk::MAX_PHASE || md->n_wave < 4 || md->n_wave > sbk::MAX_WAVE)
+    return set_error(SB_ERR_ARG, "sb_create: grid size out of range");
+  if (!md->m0 || !md->m1) return set_error(SB_ERR_ARG, "sb_create: NULL surface");
+  const double g4[4] = {md->phase0, md->dphase, md->wave0, md->dwave};
+  if (!finite_all(g4, 4) || !(md->dphase > 0) || !(md->dwave > 0))
+    return set_error(SB_ERR_ARG, "sb_create: bad grid spacing/origin");
+  if (md->cl_degree < 0 || md->cl_degree > SB_MAX_CL_DEGREE || (md->cl_degree > 0 && !md->cl_coef))
+    return set_error(SB_ERR_ARG, "sb_create: bad colour law degree");
+  if (md->cl_degree > 0 && !finite_all(md->cl_coef, md->cl_degree))
+    return set_error(SB_ERR_ARG, "sb_create: non-finite colour law");
+  if (!std::isfinite(md->cl_wave_b) || !std::isfinite(md->cl_wave_v) || md->cl_wave_v == md->cl_wave_b)
+    return set_error(SB_ERR_ARG, "sb_create: colour law reference wavelengths");
+  const size_t nsurf = (size_t)md->n_phase * md->n_wave;
+  for (size_t i = 0; i < nsurf; ++i)
+    if (!std::isfinite(md->m0[i]) || !std::isfinite(md->m1[i]))
+      return set_error(SB_ERR_ARG, "sb_create: non-finite surface value");
+
+  sb_config cfg;
+  sb_config_default(&cfg);
+  if (cfg_in) cfg = *cfg_in;
+  if (!(cfg.max_spacing > 0) || cfg.max_obs_per_fit < 1 || cfg.max_obs_per_fit > 1024 || cfg.max_slots < 1 ||
+      cfg.max_slots > 65536 || cfg.hbm_budget_bytes < 0 || cfg.iters_per_tick < 1 || cfg.fit_iters < 0 ||
+      !(cfg.lm_lambda0 > 0))
+    return set_error(SB_ERR_ARG, "sb_create: bad configuration");
+
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+
+  sb_ctx* c = new (std::nothrow) sb_ctx();
+  if (!c) return set_error(SB_ERR_NOMEM, "sb_create: host allocation");
+  c->device = device;
+  c->cfg = cfg;
+  c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+  c->max_lds = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
+
+  sbk::KModel& k = c->km;
+  k.n_phase = md->n_phase;
+  k.n_wave = md->n_wave;
+  k.row_pad = (md->n_phase + 15) / 16 * 16;
+  k.n_bands = 0;
+  k.phase0 = (float)md->phase0;
+  k.inv_dphase = (float)(1.0 / md->dphase);
+  k.wave0 = (float)md->wave0;
+  k.inv_dwave = (float)(1.0 / md->dwave);
+  k.cl_b = (float)md->cl_wave_b;
+  k.cl_inv_span = (float)(1.0 / (md->cl_wave_v - md->cl_wave_b));
+  k.cl_deg = md->cl_degree;
+  for (int n = 0; n < SB_MAX_CL_DEGREE; ++n) {
+    k.cl[n] = n < md->cl_degree ? (float)md->cl_coef[n] : 0.f;
+    k.dcl[n] = n < md->cl_degree ? (float)((n + 1) * md->cl_coef[n]) : 0.f;
+  }
+  c->wave_lo = md->wave0;
+  c->wave_hi = md->wave0 + (md->n_wave - 1) * md->dwave;
+
+  // surfaces, wavelength-major: node (a, j) -> surf[j * row_pad + a] = (M0, M1)
+  std::vector<float2> surf((size_t)k.n_wave * k.row_pad, make_float2(0.f, 0.f));
+  for (int a = 0; a < k.n_phase; ++a)
+    for (int j = 0; j < k.n_wave; ++j) {
+      const size_t src = (size_t)a * k.n_wave + j;
+      surf[(size_t)j * k.row_pad + a] = make_float2(md->m0[src], md->m1[src]);
+    }
+  const size_t pts_bytes = (size_t)SB_MAX_BANDS * SB_MAX_BAND_POINTS * sizeof(float2);
+  if ((e = hipMalloc(&c->d_surf, surf.size() * sizeof(float2))) != hipSuccess ||
+      (e = hipMalloc(&c->d_pts, pts_bytes)) != hipSuccess ||
+      (e = hipMalloc(&c->d_npts, SB_MAX_BANDS * sizeof(int))) != hipSuccess ||
+      (e = hipMalloc(&c->d_err, sizeof(int))) != hipSuccess ||
+      (e = hipMalloc(&c->d_counters, SB_N_COUNTERS * sizeof(int))) != hipSuccess) {
+    free_ctx(c);
+    return set_error(SB_ERR_NOMEM, std::string("sb_create: hipMalloc: ") + hipGetErrorString(e));
+  }
+  if ((e = hipMemcpy(c->d_surf, surf.data(), surf.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemset(c->d_pts, 0, pts_bytes)) != hipSuccess ||
+      (e = hipMemset(c->d_npts, 0, SB_MAX_BANDS * sizeof(int))) != hipSuccess ||
+      (e = hipMemset(c->d_err, 0, sizeof(int))) != hipSuccess ||
+      (e = hipMemset(c->d_counters, 0, SB_N_COUNTERS * sizeof(int))) != hipSuccess) {
+    free_ctx(c);
+    return hip_fail(e, "sb_create: upload");
+  }
+  *out = c;
+  return SB_OK;
+}
+
+sb_status sb_destroy(sb_ctx* ctx) {
+  if (!ctx) return set_error(SB_ERR_ARG, "sb_destroy: NULL context");
+  (void)hipSetDevice(ctx->device);
+  if (ctx->server) {
+    delete ctx->server;
+    ctx->server = nullptr;
+  }
+  (void)hipDeviceSynchronize();
+  free_ctx(ctx);
+  return SB_OK;
+}
+
+sb_status sb_add_band(sb_ctx* ctx, const double* wave, const double* trans, int32_t n, int32_t* band_id) {
+  if (!ctx || !band_id) return set_error(SB_ERR_ARG, "sb_add_band: NULL argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (ctx->n_bands >= SB_MAX_BANDS) return set_error(SB_ERR_ARG, "sb_add_band: registry full");
+  std::vector<double> lam, W;
+  sb_status st = sbh::build_band_grid(wave, trans, n, ctx->cfg.max_spacing, lam, W);
+  if (st != SB_OK) return st;
+  const int np = (int)lam.size();
+  // the per-supernova pipeline keeps a band's nodes in LDS: check it fits
+  const size_t need = std::max(sbk::lds_bytes(ctx->km, std::max(np, ctx->max_pts), true),
+                               sbk::fit_lds_bytes(ctx->km, std::max(np, ctx->max_pts)));
+  if (need > ctx->max_lds) return set_error(SB_ERR_ARG, "sb_add_band: band grid too large for LDS");
+  std::vector<float2> host(np);
+  for (int k = 0; k < np; ++k) host[k] = make_float2((float)lam[k], (float)W[k]);
+  hipError_t e = hipSetDevice(ctx->device);
+  const int id = ctx->n_bands;
+  if (e == hipSuccess)
+    e = hipMemcpy(ctx->d_pts + (size_t)id * SB_MAX_BAND_POINTS, host.data(), np * sizeof(float2),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ctx->d_npts + id, &np, sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "sb_add_band: upload");
+  ctx->band_lo.push_back(wave[0]);
+  ctx->band_hi.push_back(wave[n - 1]);
+  ctx->max_pts = std::max(ctx->max_pts, np);
+  ctx->n_bands = id + 1;
+  ctx->km.n_bands = ctx->n_bands;
+  ctx->sweep_bpc[0] = ctx->sweep_bpc[1] = 0;
+  *band_id = id;
+  return SB_OK;
+}
+
+static sb_status check_batch(const sb_ctx* ctx, const sb_batch* b, const char* who) {
+  const std::string w(who);
+  if (!ctx || !b) return set_error(SB_ERR_ARG, w + ": NULL argument");
+  if (b->n_sn < 0 || b->n_obs < 0) return set_error(SB_ERR_ARG, w + ": negative size");
+  if (!(b->flags & SB_OBS_BROADCAST) && b->n_sn > (1 << 24) - 1)
+    return set_error(SB_ERR_ARG, w + ": more than 2^24 - 1 supernovae in one call");
+  if (b->flags & ~(SB_OBS_BROADCAST | SB_OUT_CHI2)) return set_error(SB_ERR_ARG, w + ": unknown flags");
+  if (ctx->n_bands == 0) return set_error(SB_ERR_STATE, w + ": no band registered");
+  if (b->n_sn > 0 && (!b->z || !b->t0 || !b->x0 || !b->x1 || !b->c))
+    return set_error(SB_ERR_ARG, w + ": NULL parameter array");
+  if (b->n_obs > 0 && (!b->t || !b->band)) return set_error(SB_ERR_ARG, w + ": NULL observation array");
+  if (!(b->flags & SB_OBS_BROADCAST) && b->n_sn > 0 && !b->sn_offsets)
+    return set_error(SB_ERR_ARG, w + ": NULL sn_offsets");
+  if ((b->flags & SB_OUT_CHI2) && b->n_obs > 0 && (!b->data || !b->inv_sigma2))
+    return set_error(SB_ERR_ARG, w + ": SB_OUT_CHI2 needs data and inv_sigma2");
+  return SB_OK;
+}
+
+static sbk::KBatch make_kbatch(sb_ctx* ctx, const sb_batch* b) {
+  sbk::KBatch k{};
+  k.n_sn = b->n_sn;
+  k.n_obs = b->n_obs;
+  k.flags = b->flags;
+  k.z = b->z; k.t0 = b->t0; k.x0 = b->x0; k.x1 = b->x1; k.c = b->c;
+  k.t = b->t; k.band = b->band; k.off = b->sn_offsets;
+  k.data = b->data; k.w = b->inv_sigma2;
+  k.err = ctx->d_err;
+  return k;
+}
+
+static sb_status launch(sb_ctx* ctx, bool adj, sbk::KBatch& kb, hipStream_t st) {
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  const size_t lds = sbk::lds_bytes(ctx->km, ctx->max_pts, adj);
+  if (lds > ctx->max_lds) return set_error(SB_ERR_ARG, "bands too large for LDS");
+  const sbk::KTables tb = ctx->tables();
+  if (kb.flags & SB_OBS_BROADCAST) {
+    const int mode = adj ? 1 : 0;
+    if (ctx->sweep_bpc[mode] == 0) ctx->sweep_bpc[mode] = sbk::sweep_blocks_per_cu(adj, ctx->km, ctx->max_pts);
+    long grid = (long)ctx->n_cu * ctx->sweep_bpc[mode];
+    if (grid > kb.n_sn) grid = kb.n_sn;
+    if (grid < 1) grid = 1;
+    const unsigned slot = ctx->next_counter.fetch_add(1) % SB_N_COUNTERS;
+    kb.counter = ctx->d_counters + slot;
+    e = sbk::launch_sweep(adj, ctx->km, tb, kb, (int)grid, st);
+  } else {
+    e = sbk::launch_sn(adj, ctx->km, tb, kb, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return SB_OK;
+}
+
+sb_status sb_bandflux(sb_ctx* ctx, const sb_batch* b, float* out, void* hip_stream) {
+  sb_status st = check_batch(ctx, b, "sb_bandflux");
+  if (st != SB_OK) return st;
+  const bool chi2 = (b->flags & SB_OUT_CHI2) != 0;
+  const bool any_out = b->n_sn > 0 && (chi2 || b->n_obs > 0);
+  if (!any_out) return SB_OK;
+  if (!out) return set_error(SB_ERR_ARG, "sb_bandflux: NULL output");
+  sbk::KBatch kb = make_kbatch(ctx, b);
+  if (chi2) kb.chi2 = out; else kb.flux = out;
+  return launch(ctx, false, kb, (hipStream_t)hip_stream);
+}
+
+sb_status sb_bandflux_vjp(sb_ctx* ctx, const sb_batch* b, const float* cot, float* grad, float* flux_out,
+                          float* jac_out, float* chi2_out, void* hip_stream) {
+  sb_status st = check_batch(ctx, b, "sb_bandflux_vjp");
+  if (st != SB_OK) return st;
+  const bool chi2 = (b->flags & SB_OUT_CHI2) != 0;
+  if (b->n_sn == 0) return SB_OK;
+  if (!grad) return set_error(SB_ERR_ARG, "sb_bandflux_vjp: NULL grad");
+  if (chi2 && cot) return set_error(SB_ERR_ARG, "sb_bandflux_vjp: cotangent must be NULL with SB_OUT_CHI2");
+  if (!chi2 && !cot && b->n_obs > 0) return set_error(SB_ERR_ARG, "sb_bandflux_vjp: NULL cotangent");
+  if (!chi2 && chi2_out) return set_error(SB_ERR_ARG, "sb_bandflux_vjp: chi2_out needs SB_OUT_CHI2");
+  sbk::KBatch kb = make_kbatch(ctx, b);
+  kb.cot = cot;
+  kb.grad = grad;
+  kb.flux = flux_out;
+  kb.jac = jac_out;
+  kb.chi2 = chi2_out;
+  return launch(ctx, true, kb, (hipStream_t)hip_stream);
+}
+
+sb_status sb_device_check(sb_ctx* ctx, void* hip_stream) {
+  if (!ctx) return set_error(SB_ERR_ARG, "sb_device_check: NULL context");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)hip_stream);
+  int flags = 0;
+  if (e == hipSuccess) e = hipMemcpy(&flags, ctx->d_err, sizeof(int), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && flags) e = hipMemset(ctx->d_err, 0, sizeof(int));
+  if (e != hipSuccess) return hip_fail(e, "sb_device_check");
+  if (flags) {
+    std::string m = "device flags:";
+    if (flags & sbk::EFLAG_WINDOW) m += " band window outside the surface grid;";
+    if (flags & sbk::EFLAG_BAND) m += " band id out of range;";
+    if (flags & sbk::EFLAG_CSR) m += " malformed sn_offsets;";
+    return set_error(SB_ERR_RANGE, m);
+  }
+  return SB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+// Library-internal declarations shared by the host code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "saltbf.h"
+
+namespace sbk {
+
+constexpr int WG = 256;            // threads per workgroup (4 wave64)
+constexpr int NWAVES = WG / 64;
+constexpr int MAX_PHASE = 256;     // surface rows supported
+constexpr int MAX_WAVE = 8192;     // surface columns supported
+
+// Sticky device error bits (sb_device_check maps any of them to SB_ERR_RANGE).
+enum : int { EFLAG_WINDOW = 1, EFLAG_BAND = 2, EFLAG_CSR = 4 };
+
+// Model constants, passed by value as a kernel argument.
+struct KModel {
+  int n_phase, n_wave, row_pad, n_bands;
+  float phase0, inv_dphase, wave0, inv_dwave;
+  float cl_b, cl_inv_span;
+  int cl_deg;
+  float cl[SB_MAX_CL_DEGREE];    // a_1..a_deg
+  float dcl[SB_MAX_CL_DEGREE];   // n * a_n
+};
+
+// Device tables owned by the context.
+struct KTables {
+  const float2* surf;   // [n_wave][row_pad] of (M0, M1) at node (a, j) -> surf[j*row_pad + a]
+  const float2* pts;    // [n_bands][SB_MAX_BAND_POINTS] of (lam_k, W_k)
+  const int* npts;      // [n_bands] node count per band
+  int max_pts;          // largest node count over registered bands (sizes the LDS)
+};
+
+// One bandflux / adjoint launch.
+struct KBatch {
+  int n_sn, n_obs, flags;
+  const float *z, *t0, *x0, *x1, *c;
+  const float* t;
+  const int* band;
+  const int* off;
+  const float *data, *w, *cot;
+  float *flux, *grad, *jac, *chi2;
+  int* err;
+  int* counter;    // work counter of the persistent sweep kernel
+};
+
+// Dynamic LDS bytes of the per-supernova pipeline.
+size_t lds_bytes(const KModel& m, int max_pts, bool adj);
+
+// One workgroup per supernova (forward, or forward + adjoint).
+hipError_t launch_sn(bool adj, const KModel& m, const KTables& tb, const KBatch& b, hipStream_t st);
+
+// Persistent sweep over parameter samples sharing one observation table.
+hipError_t launch_sweep(bool adj, const KModel& m, const KTables& tb, const KBatch& b, int grid,
+                        hipStream_t st);
+int sweep_blocks_per_cu(bool adj, const KModel& m, int max_pts);
+
+// ------------------------------------------------------------------ fit server
+
+// Per-fit device state; lives in the server's slot array between launches.
+struct FitSlot {
+  int obs_off;      // first observation in the arena
+  int n_obs;
+  int iter;         // LM iterations done; -1 = not yet evaluated at the start point
+  int n_accept;
+  int status;       // SB_OK / SB_FIT_DIVERGED
+  int pad_[3];
+  float z;
+  float q[4];       // t0, ln x0, x1, c
+  float lambda;
+  float chi2;
+  float H[10];      // J^T W J, packed upper triangle (00 01 02 03 11 12 13 22 23 33)
+  float g[4];       // J^T W r
+};
+
+// A request admitted in this launch: copied from the inbox into its arena range
+// and its slot initialised by the workgroup that then runs it.
+struct AdmitHeader {
+  int slot;
+  int arena_off;
+  int n_obs;
+  int src_off;       // offset of its observations in the inbox arrays
+  float z, t0, lnx0, x1, c;
+  int pad_[3];
+};
+
+struct KFit {
+  FitSlot* slots;
+  FitSlot* results;    // finished fits of this launch, at out_idx
+  const int* active;   // slot ids of this launch
+  const int* out_idx;  // >= 0: this launch finishes the fit, write its state there
+  const int* admit;    // >= 0: index of its AdmitHeader (first launch of the fit)
+  const AdmitHeader* hdr;
+  const float* in_t;   // inbox observation arrays
+  const int* in_band;
+  const float* in_data;
+  const float* in_w;
+  int n_active;
+  int iters;           // iterations to run this launch
+  int fit_iters;       // total per fit
+  float lambda0;
+  float* t;            // arena [capacity]: observations of resident fits
+  int* band;
+  float* data;
+  float* w;            // 1/sigma^2
+  int* err;
+};
+
+hipError_t launch_fit(const KModel& m, const KTables& tb, const KFit& f, hipStream_t st);
+size_t fit_lds_bytes(const KModel& m, int max_pts);
+
+}  // namespace sbk

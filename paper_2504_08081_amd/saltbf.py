@@ -1,0 +1,367 @@
+"""Python binding of libsaltbf (the C ABI in include/saltbf.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  PyTorch provides device memory (tensor data
+pointers) and streams (the current stream is passed to every call).  If the
+library is not built, every entry point raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsaltbf.so")
+
+SB_OK, SB_PENDING, SB_CANCELLED, SB_FIT_DIVERGED = 0, 1, 2, 3
+SB_ERR_ARG, SB_ERR_RANGE, SB_ERR_DEVICE, SB_ERR_NOMEM = -1, -2, -3, -4
+SB_ERR_BUDGET, SB_ERR_STATE, SB_ERR_NOTFOUND = -5, -6, -7
+SB_OBS_BROADCAST, SB_OUT_CHI2 = 1, 2
+SB_MAX_BANDS, SB_MAX_BAND_POINTS, SB_N_PARAMS = 64, 2048, 5
+
+EXPORTED = (
+    "sb_config_default", "sb_create", "sb_destroy", "sb_add_band", "sb_band_grid", "sb_bandflux",
+    "sb_bandflux_vjp", "sb_device_check", "sb_fit_submit", "sb_fit_poll", "sb_fit_wait", "sb_fit_cancel",
+    "sb_stats", "sb_status_string", "sb_last_error",
+)
+
+_f32p = ctypes.POINTER(ctypes.c_float)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class ModelDesc(ctypes.Structure):
+    _fields_ = [("n_phase", ctypes.c_int32), ("n_wave", ctypes.c_int32),
+                ("phase0", ctypes.c_double), ("dphase", ctypes.c_double),
+                ("wave0", ctypes.c_double), ("dwave", ctypes.c_double),
+                ("m0", ctypes.c_void_p), ("m1", ctypes.c_void_p),
+                ("cl_degree", ctypes.c_int32), ("cl_coef", ctypes.c_void_p),
+                ("cl_wave_b", ctypes.c_double), ("cl_wave_v", ctypes.c_double)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("max_spacing", ctypes.c_double), ("max_obs_per_fit", ctypes.c_int32),
+                ("max_slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64),
+                ("iters_per_tick", ctypes.c_int32), ("fit_iters", ctypes.c_int32),
+                ("lm_lambda0", ctypes.c_double)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("n_sn", ctypes.c_int32), ("n_obs", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("z", ctypes.c_void_p), ("t0", ctypes.c_void_p), ("x0", ctypes.c_void_p),
+                ("x1", ctypes.c_void_p), ("c", ctypes.c_void_p),
+                ("t", ctypes.c_void_p), ("band", ctypes.c_void_p), ("sn_offsets", ctypes.c_void_p),
+                ("data", ctypes.c_void_p), ("inv_sigma2", ctypes.c_void_p)]
+
+
+class FitRequest(ctypes.Structure):
+    _fields_ = [("n_obs", ctypes.c_int32), ("t", ctypes.c_void_p), ("band", ctypes.c_void_p),
+                ("data", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
+                ("z", ctypes.c_float), ("t0", ctypes.c_float), ("x0", ctypes.c_float),
+                ("x1", ctypes.c_float), ("c", ctypes.c_float)]
+
+
+class FitResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("z", ctypes.c_float), ("t0", ctypes.c_float),
+                ("x0", ctypes.c_float), ("x1", ctypes.c_float), ("c", ctypes.c_float),
+                ("chi2", ctypes.c_float), ("iters", ctypes.c_int32), ("n_accept", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("cancelled", ctypes.c_int64), ("rejected", ctypes.c_int64), ("ticks", ctypes.c_int64),
+                ("queue_depth", ctypes.c_int32), ("active_slots", ctypes.c_int32),
+                ("bytes_in_use", ctypes.c_int64), ("budget_bytes", ctypes.c_int64),
+                ("busy_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SaltBFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_LIB = None
+
+
+def lib():
+    """The loaded libsaltbf.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        # torch ships its own HIP runtime under the same soname as the system one; importing
+        # torch first makes the library bind to that runtime, so the process holds only one.
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, st = ctypes.c_void_p, ctypes.c_int32
+        L.sb_config_default.argtypes = [ctypes.POINTER(Config)]
+        L.sb_config_default.restype = None
+        L.sb_create.argtypes = [ctypes.POINTER(ModelDesc), ctypes.POINTER(Config), ctypes.c_int, ctypes.POINTER(vp)]
+        L.sb_create.restype = st
+        L.sb_destroy.argtypes = [vp]
+        L.sb_destroy.restype = st
+        L.sb_add_band.argtypes = [vp, _f64p, _f64p, ctypes.c_int32, _i32p]
+        L.sb_add_band.restype = st
+        L.sb_band_grid.argtypes = [_f64p, _f64p, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _f32p, _f32p, _i32p]
+        L.sb_band_grid.restype = st
+        L.sb_bandflux.argtypes = [vp, ctypes.POINTER(Batch), vp, vp]
+        L.sb_bandflux.restype = st
+        L.sb_bandflux_vjp.argtypes = [vp, ctypes.POINTER(Batch), vp, vp, vp, vp, vp, vp]
+        L.sb_bandflux_vjp.restype = st
+        L.sb_device_check.argtypes = [vp, vp]
+        L.sb_device_check.restype = st
+        L.sb_fit_submit.argtypes = [vp, ctypes.POINTER(FitRequest), ctypes.POINTER(ctypes.c_uint64)]
+        L.sb_fit_submit.restype = st
+        L.sb_fit_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(FitResult)]
+        L.sb_fit_poll.restype = st
+        L.sb_fit_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(FitResult)]
+        L.sb_fit_wait.restype = st
+        L.sb_fit_cancel.argtypes = [vp, ctypes.c_uint64]
+        L.sb_fit_cancel.restype = st
+        L.sb_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.sb_stats.restype = st
+        L.sb_status_string.argtypes = [st]
+        L.sb_status_string.restype = ctypes.c_char_p
+        L.sb_last_error.argtypes = []
+        L.sb_last_error.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def _check(status, what):
+    if status < 0:
+        L = lib()
+        raise SaltBFError(status, f"{what}: {L.sb_status_string(status).decode()}: {L.sb_last_error().decode()}")
+    return status
+
+
+def default_config(**over) -> Config:
+    cfg = Config()
+    lib().sb_config_default(ctypes.byref(cfg))
+    for k, v in over.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+def band_grid(wave, trans, max_spacing=5.0):
+    """Host-only quadrature grid of a band as the library builds it: (lam_k, W_k) float32."""
+    w = np.ascontiguousarray(wave, np.float64)
+    t = np.ascontiguousarray(trans, np.float64)
+    lam = np.zeros(SB_MAX_BAND_POINTS, np.float32)
+    W = np.zeros(SB_MAX_BAND_POINTS, np.float32)
+    n = ctypes.c_int32(0)
+    _check(lib().sb_band_grid(w.ctypes.data_as(_f64p), t.ctypes.data_as(_f64p), len(w), float(max_spacing),
+                              SB_MAX_BAND_POINTS, lam.ctypes.data_as(_f32p), W.ctypes.data_as(_f32p),
+                              ctypes.byref(n)), "sb_band_grid")
+    return lam[: n.value].copy(), W[: n.value].copy()
+
+
+def _dev(x, dtype, name):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {x.dtype}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return x
+
+
+def _ptr(x):
+    return None if x is None else ctypes.c_void_p(x.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A library context: the model surfaces and the registered bands on one GPU."""
+
+    def __init__(self, m0, m1, phase0, dphase, wave0, dwave, cl_coef, cl_wave_b, cl_wave_v,
+                 config: Optional[Config] = None, device: int = 0, **config_over):
+        m0 = np.ascontiguousarray(m0, np.float32)
+        m1 = np.ascontiguousarray(m1, np.float32)
+        if m0.shape != m1.shape or m0.ndim != 2:
+            raise ValueError("m0 and m1 must be 2-D arrays of one shape")
+        cl = np.ascontiguousarray(cl_coef, np.float64)
+        d = ModelDesc(m0.shape[0], m0.shape[1], phase0, dphase, wave0, dwave,
+                      m0.ctypes.data, m1.ctypes.data, len(cl), cl.ctypes.data, cl_wave_b, cl_wave_v)
+        cfg = config if config is not None else default_config(**config_over)
+        h = ctypes.c_void_p()
+        _check(lib().sb_create(ctypes.byref(d), ctypes.byref(cfg), device, ctypes.byref(h)), "sb_create")
+        self._h = h
+        self.config = cfg
+        self.device = device
+        self.n_bands = 0
+
+    @classmethod
+    def from_model(cls, model, bands: Sequence = (), **kw):
+        """Build from an object with m0, m1, phase0, dphase, wave0, dwave, cl_coef, cl_wave_b, cl_wave_v
+        attributes and register `bands` (objects with .wave and .trans)."""
+        ctx = cls(model.m0, model.m1, model.phase0, model.dphase, model.wave0, model.dwave,
+                  model.cl_coef, model.cl_wave_b, model.cl_wave_v, **kw)
+        for b in bands:
+            ctx.add_band(b.wave, b.trans)
+        return ctx
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_band(self, wave, trans) -> int:
+        w = np.ascontiguousarray(wave, np.float64)
+        t = np.ascontiguousarray(trans, np.float64)
+        bid = ctypes.c_int32(-1)
+        _check(lib().sb_add_band(self._h, w.ctypes.data_as(_f64p), t.ctypes.data_as(_f64p), len(w),
+                                 ctypes.byref(bid)), "sb_add_band")
+        self.n_bands += 1
+        return bid.value
+
+    # ------------------------------------------------------------------ compute
+    def _batch(self, z, t0, x0, x1, c, t, band, sn_offsets, broadcast, data, inv_sigma2, chi2):
+        import torch
+        for n, v in (("z", z), ("t0", t0), ("x0", x0), ("x1", x1), ("c", c), ("t", t)):
+            _dev(v, torch.float32, n)
+        _dev(band, torch.int32, "band")
+        n_sn, n_obs = z.numel(), t.numel()
+        for n, v in (("t0", t0), ("x0", x0), ("x1", x1), ("c", c)):
+            if v.numel() != n_sn:
+                raise ValueError(f"{n} must have n_sn elements")
+        if band.numel() != n_obs:
+            raise ValueError("band must have n_obs elements")
+        if not broadcast:
+            _dev(sn_offsets, torch.int32, "sn_offsets")
+            if sn_offsets.numel() != n_sn + 1:
+                raise ValueError("sn_offsets must have n_sn + 1 elements")
+        if chi2:
+            _dev(data, torch.float32, "data")
+            _dev(inv_sigma2, torch.float32, "inv_sigma2")
+            if data.numel() != n_obs or inv_sigma2.numel() != n_obs:
+                raise ValueError("data / inv_sigma2 must have n_obs elements")
+        flags = (SB_OBS_BROADCAST if broadcast else 0) | (SB_OUT_CHI2 if chi2 else 0)
+        return Batch(n_sn, n_obs, flags, _ptr(z), _ptr(t0), _ptr(x0), _ptr(x1), _ptr(c), _ptr(t), _ptr(band),
+                     None if broadcast else _ptr(sn_offsets), _ptr(data) if chi2 else None,
+                     _ptr(inv_sigma2) if chi2 else None)
+
+    def bandflux(self, z, t0, x0, x1, c, t, band, sn_offsets=None, *, broadcast=False, data=None,
+                 inv_sigma2=None, chi2=False, out=None, stream=None):
+        """Fluxes [n_obs] ([n_sn, n_obs] with broadcast), or chi2 [n_sn] with chi2=True."""
+        import torch
+        b = self._batch(z, t0, x0, x1, c, t, band, sn_offsets, broadcast, data, inv_sigma2, chi2)
+        shape = (b.n_sn,) if chi2 else ((b.n_sn, b.n_obs) if broadcast else (b.n_obs,))
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=z.device)
+        else:
+            _dev(out, torch.float32, "out")
+            if tuple(out.shape) != shape:
+                raise ValueError(f"out must have shape {shape}")
+        _check(lib().sb_bandflux(self._h, ctypes.byref(b), _ptr(out), _stream(stream)), "sb_bandflux")
+        return out
+
+    def bandflux_vjp(self, z, t0, x0, x1, c, t, band, sn_offsets=None, cotangent=None, *, broadcast=False,
+                     data=None, inv_sigma2=None, chi2=False, want_flux=False, want_jac=False, grad=None,
+                     stream=None):
+        """Adjoint: returns dict(grad [n_sn, 5] (z, t0, x0, x1, c), flux?, jac?, chi2?)."""
+        import torch
+        b = self._batch(z, t0, x0, x1, c, t, band, sn_offsets, broadcast, data, inv_sigma2, chi2)
+        dev = z.device
+        if grad is None:
+            grad = torch.empty((b.n_sn, SB_N_PARAMS), dtype=torch.float32, device=dev)
+        nrow = b.n_sn * b.n_obs if broadcast else b.n_obs
+        flux = torch.empty(nrow, dtype=torch.float32, device=dev) if want_flux else None
+        jac = torch.empty((nrow, SB_N_PARAMS), dtype=torch.float32, device=dev) if want_jac else None
+        c2 = torch.empty(b.n_sn, dtype=torch.float32, device=dev) if chi2 else None
+        if not chi2:
+            _dev(cotangent, torch.float32, "cotangent")
+            if cotangent.numel() != nrow:
+                raise ValueError("cotangent has the wrong size")
+        _check(lib().sb_bandflux_vjp(self._h, ctypes.byref(b), None if chi2 else _ptr(cotangent), _ptr(grad),
+                                     _ptr(flux), _ptr(jac), _ptr(c2), _stream(stream)), "sb_bandflux_vjp")
+        return {"grad": grad, "flux": flux, "jac": jac, "chi2": c2}
+
+    def device_check(self, stream=None):
+        """Synchronise the stream and raise if the device flagged a range error."""
+        _check(lib().sb_device_check(self._h, _stream(stream)), "sb_device_check")
+
+    # ------------------------------------------------------------------ serving
+    def fit_submit(self, t, band, data, sigma, z, t0, x0, x1, c) -> int:
+        t = np.ascontiguousarray(t, np.float32)
+        band = np.ascontiguousarray(band, np.int32)
+        data = np.ascontiguousarray(data, np.float32)
+        sigma = np.ascontiguousarray(sigma, np.float32)
+        r = FitRequest(len(t), t.ctypes.data, band.ctypes.data, data.ctypes.data, sigma.ctypes.data,
+                       z, t0, x0, x1, c)
+        tk = ctypes.c_uint64(0)
+        _check(lib().sb_fit_submit(self._h, ctypes.byref(r), ctypes.byref(tk)), "sb_fit_submit")
+        return tk.value
+
+    def fit_poll(self, ticket):
+        res = FitResult()
+        st = _check(lib().sb_fit_poll(self._h, ticket, ctypes.byref(res)), "sb_fit_poll")
+        return None if st == SB_PENDING else res
+
+    def fit_wait(self, ticket, timeout_s=10.0):
+        res = FitResult()
+        st = _check(lib().sb_fit_wait(self._h, ticket, timeout_s, ctypes.byref(res)), "sb_fit_wait")
+        return None if st == SB_PENDING else res
+
+    def fit_cancel(self, ticket):
+        _check(lib().sb_fit_cancel(self._h, ticket), "sb_fit_cancel")
+
+    def stats(self):
+        s = Stats()
+        _check(lib().sb_stats(self._h, ctypes.byref(s)), "sb_stats")
+        return s.as_dict()
+
+
+def _saltbandflux_function():
+    import torch
+
+    class SaltBandflux(torch.autograd.Function):
+        """flux = bandflux(z, t0, x0, x1, c; observations); backward through the hand-written adjoint."""
+
+        @staticmethod
+        def forward(fctx, lib_ctx, z, t0, x0, x1, c, t, band, sn_offsets):
+            fctx.lib_ctx = lib_ctx
+            fctx.save_for_backward(z, t0, x0, x1, c, t, band, sn_offsets)
+            return lib_ctx.bandflux(z, t0, x0, x1, c, t, band, sn_offsets)
+
+        @staticmethod
+        def backward(fctx, gflux):
+            z, t0, x0, x1, c, t, band, off = fctx.saved_tensors
+            g = fctx.lib_ctx.bandflux_vjp(z, t0, x0, x1, c, t, band, off, gflux.contiguous())["grad"]
+            return (None, g[:, 0], g[:, 1], g[:, 2], g[:, 3], g[:, 4], None, None, None)
+
+    return SaltBandflux
+
+
+_SBF = None
+
+
+def salt_bandflux(lib_ctx: Context, z, t0, x0, x1, c, t, band, sn_offsets):
+    """Differentiable bandflux (torch.autograd) over the library's forward and adjoint kernels."""
+    global _SBF
+    if _SBF is None:
+        _SBF = _saltbandflux_function()
+    return _SBF.apply(lib_ctx, z, t0, x0, x1, c, t, band, sn_offsets)

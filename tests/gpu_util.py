@@ -1,0 +1,69 @@
+"""Helpers of the GPU tests: moving synthetic batches to the device, error metrics."""
+import numpy as np
+import pytest
+
+FLUX_TOL = 1e-5    # max relative error of an FP32 flux against the FP64 oracle
+GRAD_TOL = 1e-4    # max relative error of an FP32 (scaled) gradient against the FP64 oracle
+PARAM_SCALE = np.array([0.1, 1.0, 1.0, 1.0, 0.1])   # z, t0 [d], x0 (times x0), x1, c
+
+
+def torch_or_skip():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    return torch
+
+
+def to_dev(batch, torch):
+    d = "cuda"
+    return dict(z=torch.from_numpy(np.ascontiguousarray(batch.z, np.float32)).to(d),
+                t0=torch.from_numpy(np.ascontiguousarray(batch.t0, np.float32)).to(d),
+                x0=torch.from_numpy(np.ascontiguousarray(batch.x0, np.float32)).to(d),
+                x1=torch.from_numpy(np.ascontiguousarray(batch.x1, np.float32)).to(d),
+                c=torch.from_numpy(np.ascontiguousarray(batch.c, np.float32)).to(d),
+                t=torch.from_numpy(np.ascontiguousarray(batch.t, np.float32)).to(d),
+                band=torch.from_numpy(np.ascontiguousarray(batch.band, np.int32)).to(d),
+                sn_offsets=torch.from_numpy(np.ascontiguousarray(batch.sn_offsets, np.int32)).to(d))
+
+
+def flux_rel_err(f_gpu, f64, offsets):
+    """|f - f64| / max(|f64|, 1e-3 max_{j in SN} |f64_j|), per observation."""
+    f_gpu = np.asarray(f_gpu, np.float64)
+    f64 = np.asarray(f64, np.float64)
+    floor = np.zeros_like(f64)
+    for s in range(len(offsets) - 1):
+        lo, hi = int(offsets[s]), int(offsets[s + 1])
+        if hi > lo:
+            floor[lo:hi] = 1e-3 * np.abs(f64[lo:hi]).max()
+    den = np.maximum(np.abs(f64), floor)
+    den = np.where(den > 0, den, 1.0)
+    return np.abs(f_gpu - f64) / den
+
+
+def grad_rel_err(g_gpu, g64, x0):
+    """Scaled gradients g * (0.1, 1 d, x0, 1, 0.1); per supernova and component, relative to
+    max(|g64|, 1e-3 * max over the supernova's components)."""
+    sc = PARAM_SCALE[None, :] * np.ones((len(x0), 1))
+    sc[:, 2] = np.asarray(x0, np.float64)
+    a = np.asarray(g_gpu, np.float64) * sc
+    b = np.asarray(g64, np.float64) * sc
+    floor = 1e-3 * np.abs(b).max(axis=1, keepdims=True)
+    den = np.maximum(np.abs(b), floor)
+    den = np.where(den > 0, den, 1.0)
+    return np.abs(a - b) / den
+
+
+def jac_rel_err(j_gpu, j64, x0_per_obs, offsets=None):
+    """Per-observation scaled Jacobian rows: relative error with a floor at 1e-2 of the row's largest
+    scaled partial.  Each partial of the bandflux is a signed combination of terms bounded by that
+    row scale (the z partial, for one, cancels an amplitude term against a wavelength-stretch term),
+    and FP32 sums of node values give those terms ~1e-6 of the row scale; the floor turns the 1e-4
+    relative bound into a 1e-6 row-scale bound for entries that cancel to near zero."""
+    sc = PARAM_SCALE[None, :] * np.ones((len(x0_per_obs), 1))
+    sc[:, 2] = x0_per_obs
+    a = np.asarray(j_gpu, np.float64) * sc
+    b = np.asarray(j64, np.float64) * sc
+    floor = 1e-2 * np.abs(b).max(axis=1, keepdims=True)
+    den = np.maximum(np.abs(b), floor)
+    den = np.where(den > 0, den, 1.0)
+    return np.abs(a - b) / den

@@ -1,0 +1,71 @@
+"""The C-ABI library loads, exports every declared symbol, and its host-only band
+grid matches the oracle's (CPU only; no compute call needs a GPU here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "saltbf.h")
+
+
+def _lib():
+    from paper_2504_08081_amd import saltbf
+    if not os.path.exists(saltbf.LIB_PATH):
+        pytest.fail("libsaltbf.so is not built (run __graft_entry__.build())")
+    return saltbf
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sb_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    sb = _lib()
+    L = ctypes.CDLL(sb.LIB_PATH)
+    decl = declared_functions()
+    assert len(decl) >= 15
+    for name in decl:
+        assert hasattr(L, name), name
+    assert set(decl) == set(sb.EXPORTED)
+
+
+def test_status_strings():
+    sb = _lib()
+    L = sb.lib()
+    for st in (0, 1, 2, 3, -1, -2, -3, -4, -5, -6, -7):
+        assert len(L.sb_status_string(st)) > 0
+    cfg = sb.default_config()
+    assert cfg.max_spacing == 5.0 and cfg.fit_iters == 50 and cfg.max_obs_per_fit == 256
+
+
+@pytest.mark.parametrize("nb,idx", [(4, 0), (6, 2), (6, 5)])
+def test_band_grid_matches_oracle(nb, idx):
+    sb = _lib()
+    b = synth.make_bands(nb)[idx]
+    lam, W = sb.band_grid(b.wave, b.trans, 5.0)
+    lam64, T64, w64 = oracle.band_grid(b.wave, b.trans, 5.0)
+    assert len(lam) == len(lam64)
+    assert np.array_equal(lam, lam64.astype(np.float32))
+    W64 = w64 * lam64 * T64 / oracle.HC
+    np.testing.assert_allclose(W.astype(np.float64), W64, rtol=1.2e-7, atol=0)
+
+
+def test_band_grid_errors():
+    sb = _lib()
+    with pytest.raises(sb.SaltBFError) as e:
+        sb.band_grid([1.0, 1.0, 2.0], [1, 1, 1])
+    assert e.value.status == sb.SB_ERR_ARG
+    with pytest.raises(sb.SaltBFError):
+        sb.band_grid([1.0, 2.0], [1.0, -1.0])
+    with pytest.raises(sb.SaltBFError):
+        sb.band_grid([0.0, 20000.0], [1.0, 1.0])   # more nodes than SB_MAX_BAND_POINTS
+    lam, W = sb.band_grid([3.0, 5.0, 7.0], [0.5, 1.0, 0.25], 1.0)
+    np.testing.assert_array_equal(lam, np.float32([3, 4, 5, 6, 7]))

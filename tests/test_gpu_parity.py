@@ -1,0 +1,378 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by element.
+
+Tolerances: fluxes <= 1e-5 relative, gradients and Jacobians <= 1e-4 relative
+(scaled parameters), as stated in tests/gpu_util.py.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import (FLUX_TOL, GRAD_TOL, flux_rel_err, grad_rel_err, jac_rel_err, to_dev,
+                      torch_or_skip)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return torch_or_skip()
+
+
+@pytest.fixture(scope="module")
+def sb():
+    from paper_2504_08081_amd import saltbf
+    saltbf.lib()   # raises if the library is not built
+    return saltbf
+
+
+@pytest.fixture(scope="module")
+def ctx4(sb, torch, model, bands4):
+    return sb.Context.from_model(model, bands4)
+
+
+@pytest.fixture(scope="module")
+def ctx6(sb, torch, model, bands6):
+    return sb.Context.from_model(model, bands6)
+
+
+@pytest.fixture(scope="module")
+def o4(model, bands4):
+    return oracle.Oracle(model, bands4)
+
+
+@pytest.fixture(scope="module")
+def o6(model, bands6):
+    return oracle.Oracle(model, bands6)
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    return synth.config2()
+
+
+def run_fwd(ctx, batch, torch):
+    d = to_dev(batch, torch)
+    f = ctx.bandflux(**d)
+    ctx.device_check()
+    return f.cpu().numpy()
+
+
+def run_jac(ctx, batch, torch, cot=None):
+    d = to_dev(batch, torch)
+    if cot is None:
+        cot = np.zeros(batch.n_obs, np.float32)
+    r = ctx.bandflux_vjp(**d, cotangent=torch.from_numpy(np.float32(cot)).cuda(), want_flux=True, want_jac=True)
+    ctx.device_check()
+    return r["flux"].cpu().numpy(), r["jac"].cpu().numpy(), r["grad"].cpu().numpy()
+
+
+def x0_per_obs(batch):
+    return np.repeat(batch.x0.astype(np.float64), np.diff(batch.sn_offsets))
+
+
+# ----------------------------------------------------------------------------- workload 1
+
+def test_cfg1_forward_all_40(ctx4, o4, torch):
+    b = synth.config1()
+    print("case: config1 forward, 40 obs", flush=True)
+    f = run_fwd(ctx4, b, torch)
+    f64 = o4.bandflux(b)
+    err = flux_rel_err(f, f64, b.sn_offsets)
+    print(f"cfg1 flux rel err max {err.max():.3e} median {np.median(err):.3e}")
+    assert err.max() <= FLUX_TOL
+
+
+def test_cfg1_jacobian_rows(ctx4, o4, torch):
+    b = synth.config1()
+    f, J, _ = run_jac(ctx4, b, torch)
+    f64, J64 = o4.jac(b)
+    assert flux_rel_err(f, f64, b.sn_offsets).max() <= FLUX_TOL
+    err = jac_rel_err(J, J64, x0_per_obs(b), b.sn_offsets)
+    print(f"cfg1 jacobian rel err max per param {err.max(axis=0)}")
+    assert err.max() <= GRAD_TOL
+
+
+# ----------------------------------------------------------------------------- small full batch
+
+def test_small_batch_every_result(ctx6, o6, torch):
+    """A 96-supernova batch: every flux, Jacobian row and cotangent gradient against the oracle."""
+    b = synth.random_batch(31, 96, 1, 300, synth.make_bands(6), synth.make_model())
+    g = np.random.default_rng(7)
+    cot = g.normal(size=b.n_obs).astype(np.float32)
+    f, J, grad = run_jac(ctx6, b, torch, cot)
+    f64, J64 = o6.jac(b)
+    g64 = oracle.segment_sum(cot.astype(np.float64)[:, None] * J64, b.sn_offsets)
+    ef = flux_rel_err(f, f64, b.sn_offsets)
+    ej = jac_rel_err(J, J64, x0_per_obs(b), b.sn_offsets)
+    eg = grad_rel_err(grad, g64, b.x0)
+    print(f"small batch: flux {ef.max():.3e} jac {ej.max():.3e} grad {eg.max():.3e}")
+    assert ef.max() <= FLUX_TOL and ej.max() <= GRAD_TOL and eg.max() <= GRAD_TOL
+    f_fwd = run_fwd(ctx6, b, torch)
+    assert flux_rel_err(f_fwd, f64, b.sn_offsets).max() <= FLUX_TOL
+
+
+# ----------------------------------------------------------------------------- workloads 2 and 3
+
+def sample_sns(batch, n=40, seed=3):
+    n_s = np.diff(batch.sn_offsets)
+    g = np.random.default_rng(seed)
+    pick = set(g.choice(batch.n_sn, n, replace=False).tolist())
+    pick |= {int(np.argmax(n_s)), int(np.argmin(n_s)), int(np.argmax(batch.z)), int(np.argmin(batch.z)),
+             0, batch.n_sn - 1}
+    return np.array(sorted(pick))
+
+
+def test_cfg2_forward_full_size_sampled(ctx6, o6, cfg2, torch):
+    print(f"case: config2 forward, {cfg2.n_sn} SN, {cfg2.n_obs} obs", flush=True)
+    f = run_fwd(ctx6, cfg2, torch)
+    assert np.all(np.isfinite(f))
+    idx = sample_sns(cfg2)
+    sub = cfg2.subset(idx)
+    f64 = o6.bandflux(sub)
+    sel = np.concatenate([np.arange(cfg2.sn_offsets[s], cfg2.sn_offsets[s + 1]) for s in idx])
+    err = flux_rel_err(f[sel], f64, sub.sn_offsets)
+    print(f"cfg2 sampled {len(idx)} SN / {len(sel)} obs: flux rel err max {err.max():.3e} "
+          f"p99 {np.percentile(err, 99):.3e} median {np.median(err):.3e}")
+    assert err.max() <= FLUX_TOL
+
+
+def test_cfg3_chi2_gradient_full_size_sampled(ctx6, o6, cfg2, torch):
+    """Workload 3: chi-square gradient at perturbed parameters, full batch on the GPU,
+    sampled supernovae against the oracle's analytic FP64 gradient."""
+    print("case: config3 chi2 gradient", flush=True)
+    truth = cfg2
+    ev = synth.perturb(truth)
+    idx = sample_sns(truth, n=32, seed=5)
+    sub_true = truth.subset(idx)
+    f_true = o6.bandflux(sub_true)
+    normals = synth.noise_draws(sub_true.n_obs)
+    d_sub, _, w_sub = synth.make_data(f_true, sub_true.sn_offsets, normals)
+    data = np.zeros(truth.n_obs, np.float32)
+    w = np.ones(truth.n_obs, np.float32)
+    sel = np.concatenate([np.arange(truth.sn_offsets[s], truth.sn_offsets[s + 1]) for s in idx])
+    data[sel] = d_sub
+    w[sel] = w_sub
+    d = to_dev(ev, torch)
+    r = ctx6.bandflux_vjp(**d, chi2=True, data=torch.from_numpy(data).cuda(), inv_sigma2=torch.from_numpy(w).cuda(),
+                          want_flux=True)
+    ctx6.device_check()
+    grad = r["grad"].cpu().numpy()[idx]
+    chi2 = r["chi2"].cpu().numpy()[idx]
+    sub_ev = ev.subset(idx)
+    f64, c64, g64 = o6.chi2_grad(sub_ev, d_sub, w_sub)
+    eg = grad_rel_err(grad, g64, sub_ev.x0)
+    ec = np.abs(chi2 - c64) / np.abs(c64)
+    ef = flux_rel_err(r["flux"].cpu().numpy()[sel], f64, sub_ev.sn_offsets)
+    print(f"cfg3: grad rel err max {eg.max():.3e} (per param {eg.max(axis=0)}), chi2 {ec.max():.3e}, flux {ef.max():.3e}")
+    assert eg.max() <= GRAD_TOL
+    assert ec.max() <= 1e-4
+    assert ef.max() <= FLUX_TOL
+
+
+def test_run_twice_bitwise(ctx6, cfg2, torch):
+    d = to_dev(cfg2, torch)
+    cot = torch.ones(cfg2.n_obs, dtype=torch.float32, device="cuda")
+    a = ctx6.bandflux_vjp(**d, cotangent=cot, want_flux=True)
+    b = ctx6.bandflux_vjp(**d, cotangent=cot, want_flux=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a["grad"], b["grad"]) and torch.equal(a["flux"], b["flux"])
+    f = ctx6.bandflux(**d)
+    torch.cuda.synchronize()
+    # forward-only and forward+adjoint kernels agree to rounding
+    rel = ((f - a["flux"]).abs() / a["flux"].abs().clamp_min(1e-30)).max().item()
+    assert rel < 1e-6
+
+
+# ----------------------------------------------------------------------------- autograd
+
+def test_autograd_function(ctx6, torch):
+    from paper_2504_08081_amd.saltbf import salt_bandflux
+    b = synth.random_batch(33, 20, 5, 60, synth.make_bands(6), synth.make_model())
+    d = to_dev(b, torch)
+    params = [d[k].clone().requires_grad_(True) for k in ("z", "t0", "x0", "x1", "c")]
+    f = salt_bandflux(ctx6, *params, d["t"], d["band"], d["sn_offsets"])
+    g = torch.randn_like(f)
+    f.backward(g)
+    r = ctx6.bandflux_vjp(**d, cotangent=g.contiguous())
+    torch.cuda.synchronize()
+    for q, p in enumerate(params):
+        assert torch.equal(p.grad, r["grad"][:, q])
+    # loose finite-difference sanity check in FP32 (FP32 differences cannot reach 1e-4)
+    for q, h in ((3, 1e-2), (4, 1e-3)):
+        pp = [x.detach().clone() for x in params]
+        pm = [x.detach().clone() for x in params]
+        pp[q] += h
+        pm[q] -= h
+        fp = ctx6.bandflux(*pp, d["t"], d["band"], d["sn_offsets"])
+        fm = ctx6.bandflux(*pm, d["t"], d["band"], d["sn_offsets"])
+        fd = ((fp - fm) * g).cpu().numpy().astype(np.float64)
+        fd = oracle.segment_sum(fd, b.sn_offsets) / (2 * h)
+        an = params[q].grad.cpu().numpy()
+        assert np.max(np.abs(fd - an)) <= 1e-2 * np.max(np.abs(an))
+
+
+# ----------------------------------------------------------------------------- closed forms through the GPU
+
+def test_tiny_exact_case_gpu(sb, torch):
+    import json
+    import os
+    from fractions import Fraction
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "tiny_exact.json")))
+    S = fx["surface"]
+    ctx = sb.Context(np.float32(S["m0"]), np.float32(S["m1"]), S["phase0"], S["dphase"], S["wave0"], S["dwave"],
+                     [0.0], 0.0, 1.0, max_spacing=fx["band"]["spacing"])
+    ctx.add_band(fx["band"]["wave"], fx["band"]["trans"])
+    P = fx["params"]
+    b = synth.Batch(np.float32([P["z"]]), np.float32([P["t0"]]), np.float32([P["x0"]]), np.float32([P["x1"]]),
+                    np.float32([P["c"]]), np.float32([fx["obs_t"]]), np.int32([0]), np.int32([0, 1]))
+    f = run_fwd(ctx, b, torch)
+    gold = Fraction(fx["expected_flux_times_hc"]["num"], fx["expected_flux_times_hc"]["den"])
+    want = float(gold) / oracle.HC
+    assert abs(f[0] - want) <= 2e-6 * want
+    ctx.close()
+
+
+@pytest.mark.parametrize("z", [0.05, 0.4, 0.9])
+def test_flat_spectrum_tophat_gpu(sb, torch, z):
+    """M0 = K, top-hat band: f = x0 K (b^2 - a^2) / (2 hc (1+z)) and df/dz = -f/(1+z)."""
+    K = 0.75
+    m0 = np.full((71, 721), K, np.float32)
+    ctx = sb.Context(m0, np.zeros_like(m0), -20.0, 1.0, 2000.0, 10.0, [-0.9, 0.1, 0.01], 4302.57, 5428.55)
+    a, bnd = 4000.0, 5230.0
+    tb = synth.tophat_band(a, bnd)
+    ctx.add_band(tb.wave, tb.trans)
+    t = np.float32([3.0, 17.25, -9.5, 40.0])
+    b = synth.Batch(np.float32([z]), np.float32([1.0]), np.float32([3e-5]), np.float32([0.0]), np.float32([0.0]),
+                    t, np.zeros(4, np.int32), np.int32([0, 4]))
+    f, J, _ = run_jac(ctx, b, torch)
+    zf, x0f = float(np.float32(z)), float(np.float32(3e-5))
+    want = x0f * K * (bnd ** 2 - a ** 2) / (2 * oracle.HC * (1 + zf))
+    assert np.max(np.abs(f - want)) <= 1e-5 * want
+    assert np.max(np.abs(J[:, 0] + want / (1 + zf))) <= 1e-4 * want
+    ctx.close()
+
+
+# ----------------------------------------------------------------------------- edge cases
+
+def test_edge_cases(ctx6, o6, torch, sb, model):
+    """Empty supernovae, phases outside and on the edges of the grid, edge cells."""
+    bands = synth.make_bands(6)
+    zs = [0.0, 0.2, 0.5, 0.1]
+    t_lists = [
+        [-30.0, -20.0, -19.5, -19.0, 0.0, 49.5, 50.0, 50.5, 80.0],   # z=0: phases exact in FP32
+        [],                                                        # empty supernova
+        [-19.99, 49.99, 10.0],
+        [5.0],
+    ]
+    ts, bs = [], []
+    for z, tl in zip(zs, t_lists):
+        ts.append(np.float32(np.array(tl) * (1 + np.float32(z))))
+        bs.append(np.full(len(tl), 3, np.int32))
+    off = np.zeros(len(zs) + 1, np.int32)
+    off[1:] = np.cumsum([len(x) for x in ts])
+    b = synth.Batch(np.float32(zs), np.float32(np.zeros(4)), np.float32([1e-5] * 4), np.float32([0.3, 0, -1, 2]),
+                    np.float32([0.05, 0, -0.1, 0.2]), np.concatenate(ts).astype(np.float32),
+                    np.concatenate(bs), off)
+    f, J, grad = run_jac(ctx6, b, torch, np.ones(b.n_obs, np.float32))
+    f64, J64 = o6.jac(b)
+    assert np.all(f[f64 == 0] == 0)
+    assert flux_rel_err(f, f64, b.sn_offsets).max() <= FLUX_TOL
+    assert jac_rel_err(J, J64, x0_per_obs(b), b.sn_offsets).max() <= GRAD_TOL
+    assert np.all(grad[1] == 0)
+    ff = run_fwd(ctx6, b, torch)
+    assert flux_rel_err(ff, f64, b.sn_offsets).max() <= FLUX_TOL
+    # no supernova: nothing to do
+    e = synth.Batch(np.float32([]), np.float32([]), np.float32([]), np.float32([]), np.float32([]),
+                    np.float32([]), np.int32([]), np.int32([0]))
+    d = to_dev(e, torch)
+    ctx6.bandflux(**d)
+    ctx6.device_check()
+
+
+def test_range_errors_are_flagged(ctx6, torch, sb):
+    """A band id beyond the registry, or a rest window outside the surface, gives NaN and SB_ERR_RANGE."""
+    ctx6.device_check()
+    b = synth.Batch(np.float32([0.2, 0.95]), np.float32([0, 0]), np.float32([1e-5, 1e-5]), np.float32([0, 0]),
+                    np.float32([0, 0]), np.float32([1.0, 2.0, 1.0, 2.0]), np.int32([1, 17, 0, 1]),
+                    np.int32([0, 2, 4]))
+    f = ctx6.bandflux(**to_dev(b, torch)).cpu().numpy()
+    with pytest.raises(sb.SaltBFError) as e:
+        ctx6.device_check()
+    assert e.value.status == sb.SB_ERR_RANGE
+    assert np.isfinite(f[0]) and np.isnan(f[1])     # band 17 does not exist
+    assert np.isnan(f[2]) and np.isfinite(f[3])     # band 0 at z = 0.95 leaves the grid
+    ctx6.device_check()                              # flags were cleared
+    # malformed CSR offsets
+    b2 = synth.Batch(np.float32([0.2]), np.float32([0]), np.float32([1e-5]), np.float32([0]), np.float32([0]),
+                     np.float32([1.0]), np.int32([1]), np.int32([0, 5]))
+    r = ctx6.bandflux_vjp(**to_dev(b2, torch), cotangent=torch.ones(1, device="cuda"))
+    with pytest.raises(sb.SaltBFError):
+        ctx6.device_check()
+    assert np.all(np.isnan(r["grad"].cpu().numpy()))
+
+
+def test_host_argument_errors(ctx6, torch, sb):
+    import ctypes
+    b = synth.config1()
+    d = to_dev(b, torch)
+    with pytest.raises(TypeError):
+        ctx6.bandflux(**{**d, "t": d["t"].cpu()})
+    with pytest.raises(TypeError):
+        ctx6.bandflux_vjp(**d, cotangent=None)
+    L = sb.lib()
+    assert L.sb_bandflux(ctx6._h, None, None, None) == sb.SB_ERR_ARG
+    batch = ctx6._batch(d["z"], d["t0"], d["x0"], d["x1"], d["c"], d["t"], d["band"], d["sn_offsets"],
+                        False, None, None, False)
+    assert L.sb_bandflux(ctx6._h, ctypes.byref(batch), None, None) == sb.SB_ERR_ARG
+    batch.flags = 64
+    out = torch.empty(b.n_obs, device="cuda")
+    assert L.sb_bandflux(ctx6._h, ctypes.byref(batch), ctypes.c_void_p(out.data_ptr()), None) == sb.SB_ERR_ARG
+    assert len(L.sb_last_error()) > 0
+
+
+# ----------------------------------------------------------------------------- sweep (workload 5)
+
+def test_sweep_matches_plain_kernel_and_oracle(ctx6, o6, torch):
+    """Persistent broadcast sweep == per-supernova kernel on the materialised batch (bitwise),
+    and both match the oracle on sampled parameter sets."""
+    sw = synth.config5a(n_samples=4096)
+    smp = sw.samples
+    n_obs = len(sw.obs_t)
+    f_true = o6.bandflux(synth.Batch(np.float32([sw.theta_true[0]]), np.float32([sw.theta_true[1]]),
+                                     np.float32([sw.theta_true[2]]), np.float32([sw.theta_true[3]]),
+                                     np.float32([sw.theta_true[4]]), sw.obs_t, sw.obs_band, np.int32([0, n_obs])))
+    data, _, w = synth.make_data(f_true, [0, n_obs], synth.noise_draws(n_obs, k=55))
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    P = dict(z=dv(smp.z), t0=dv(smp.t0), x0=dv(smp.x0), x1=dv(smp.x1), c=dv(smp.c))
+    t, band = dv(sw.obs_t), dv(sw.obs_band)
+    chi_sw = ctx6.bandflux(**P, t=t, band=band, broadcast=True, chi2=True, data=dv(data), inv_sigma2=dv(w))
+    flux_sw = ctx6.bandflux(**P, t=t, band=band, broadcast=True)
+    # the same work as a plain CSR batch
+    n = smp.n_sn
+    tt = t.repeat(n)
+    bb = band.repeat(n)
+    off = torch.arange(0, (n + 1) * n_obs, n_obs, dtype=torch.int32, device="cuda")
+    chi_pl = ctx6.bandflux(**P, t=tt, band=bb, sn_offsets=off, chi2=True, data=dv(data).repeat(n),
+                           inv_sigma2=dv(w).repeat(n))
+    flux_pl = ctx6.bandflux(**P, t=tt, band=bb, sn_offsets=off)
+    ctx6.device_check()
+    assert torch.equal(chi_sw, chi_pl)
+    assert torch.equal(flux_sw.reshape(-1), flux_pl)
+    # oracle on sampled parameter sets
+    pick = np.random.default_rng(9).choice(n, 24, replace=False)
+    F = flux_sw.cpu().numpy()
+    C = chi_sw.cpu().numpy()
+    for s in pick:
+        bs = synth.Batch(smp.z[[s]], smp.t0[[s]], smp.x0[[s]], smp.x1[[s]], smp.c[[s]], sw.obs_t, sw.obs_band,
+                         np.int32([0, n_obs]))
+        f64 = o6.bandflux(bs)
+        assert flux_rel_err(F[s], f64, [0, n_obs]).max() <= FLUX_TOL
+        c64 = np.sum((f64 - data) ** 2 * w)
+        assert abs(C[s] - c64) <= 1e-4 * c64
+    # adjoint sweep against the per-supernova adjoint
+    g_sw = ctx6.bandflux_vjp(**P, t=t, band=band, broadcast=True, chi2=True, data=dv(data), inv_sigma2=dv(w))
+    g_pl = ctx6.bandflux_vjp(**P, t=tt, band=bb, sn_offsets=off, chi2=True, data=dv(data).repeat(n),
+                             inv_sigma2=dv(w).repeat(n))
+    torch.cuda.synchronize()
+    assert torch.equal(g_sw["grad"], g_pl["grad"]) and torch.equal(g_sw["chi2"], g_pl["chi2"])

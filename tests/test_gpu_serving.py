@@ -1,0 +1,191 @@
+"""GPU tests of the continuous-batching fit server (sb_fit_submit / poll / wait / cancel).
+
+Fits are checked against the FP64 oracle's Levenberg-Marquardt fit; a fit's
+result must not depend on the other fits sharing its launches, on the byte
+budget, or on how its iterations are split over launches.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import torch_or_skip
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return torch_or_skip()
+
+
+@pytest.fixture(scope="module")
+def sb(torch):
+    from paper_2504_08081_amd import saltbf
+    saltbf.lib()
+    return saltbf
+
+
+@pytest.fixture(scope="module")
+def o6(model, bands6):
+    return oracle.Oracle(model, bands6)
+
+
+@pytest.fixture(scope="module")
+def requests(o6):
+    """Workload-4 requests with noisy data built from the oracle's true fluxes."""
+    reqs = synth.config4_requests(40, k=44)
+    out = []
+    for r in reqs:
+        b = single_batch(r)
+        f = o6.bandflux(b)
+        d, sig, w = synth.make_data(f, b.sn_offsets, r.normals)
+        out.append((r, d, sig, w))
+    return out
+
+
+def single_batch(r, theta=None):
+    th = r.theta_true if theta is None else theta
+    return synth.Batch(np.float32([r.z]), np.float32([th[0]]), np.float32([th[1]]), np.float32([th[2]]),
+                       np.float32([th[3]]), r.t, r.band, np.int32([0, len(r.t)]))
+
+
+def submit(ctx, item):
+    r, d, sig, _ = item
+    return ctx.fit_submit(r.t, r.band, d, sig, r.z, *r.theta_init)
+
+
+def result_key(res):
+    return (res.status, res.t0, res.x0, res.x1, res.c, res.chi2, res.iters, res.n_accept)
+
+
+def run_all(ctx, items, timeout=60.0):
+    tks = [submit(ctx, it) for it in items]
+    res = [ctx.fit_wait(tk, timeout) for tk in tks]
+    assert all(r is not None for r in res), "fit did not finish in time"
+    return res
+
+
+def test_fits_match_oracle(sb, o6, model, bands6, requests):
+    """Every GPU fit against the FP64 LM fit from the same start: parameters within 1e-2 of their
+    statistical uncertainty, chi2 within 1e-4."""
+    ctx = sb.Context.from_model(model, bands6)
+    items = requests[:12]
+    res = run_all(ctx, items)
+    fo = oracle.FitOracle(o6)
+    worst = 0.0
+    for (r, d, sig, w), g in zip(items, res):
+        assert g.status == sb.SB_OK and g.iters == 50
+        ref = fo.fit(single_batch(r), r.z, r.theta_init, d, w)
+        th = ref["theta"]
+        q64 = np.array([th[0], np.log(th[1]), th[2], th[3]])
+        qg = np.array([g.t0, np.log(g.x0), g.x1, g.c])
+        _, H, _ = fo.evaluate(single_batch(r), r.z, q64, d, w)
+        sig_q = np.sqrt(np.diag(np.linalg.inv(H)))
+        dev = np.abs(qg - q64) / sig_q
+        worst = max(worst, dev.max())
+        assert dev.max() <= 1e-2, (dev, g.as_dict(), ref)
+        assert abs(g.chi2 - ref["chi2"]) <= 1e-4 * ref["chi2"]
+    print(f"fit parity: max |dq|/sigma_q = {worst:.2e}")
+    ctx.close()
+
+
+def test_alone_vs_in_the_mix_bitwise(sb, model, bands6, requests):
+    """A fit alone and the same fit among 30 others sharing its launches give identical results."""
+    ctx = sb.Context.from_model(model, bands6)
+    probe = requests[5]
+    alone = run_all(ctx, [probe])[0]
+    mix_items = requests[10:25] + [probe] + requests[25:40]
+    mixed = run_all(ctx, mix_items)
+    assert result_key(mixed[15]) == result_key(alone)
+    st = ctx.stats()
+    assert st["completed"] == 32 and st["queue_depth"] == 0 and st["active_slots"] == 0
+    ctx.close()
+
+
+def test_budget_and_tick_split_do_not_change_results(sb, model, bands6, requests):
+    """A 64 KiB budget forces queueing; 7 iterations per launch splits fits differently; results match."""
+    items = requests[:16]
+    ref_ctx = sb.Context.from_model(model, bands6)
+    ref = run_all(ref_ctx, items)
+    ref_ctx.close()
+    small = sb.Context.from_model(model, bands6, hbm_budget_bytes=64 * 1024)
+    res = run_all(small, items)
+    st = small.stats()
+    small.close()
+    assert [result_key(a) for a in res] == [result_key(b) for b in ref]
+    assert st["ticks"] > 5
+    split = sb.Context.from_model(model, bands6, iters_per_tick=7)
+    res2 = run_all(split, items)
+    split.close()
+    assert [result_key(a) for a in res2] == [result_key(b) for b in ref]
+
+
+def test_invalid_requests_rejected(sb, model, bands6, requests):
+    ctx = sb.Context.from_model(model, bands6, hbm_budget_bytes=4096)
+    r, d, sig, _ = requests[0]
+
+    def expect(status, **kw):
+        a = dict(t=r.t, band=r.band, data=d, sigma=sig, z=r.z, t0=r.theta_init[0], x0=r.theta_init[1],
+                 x1=r.theta_init[2], c=r.theta_init[3])
+        a.update(kw)
+        with pytest.raises(sb.SaltBFError) as e:
+            ctx.fit_submit(**a)
+        assert e.value.status == status
+
+    n = len(r.t)
+    expect(sb.SB_ERR_ARG, band=np.full(n, 9, np.int32))
+    expect(sb.SB_ERR_ARG, sigma=np.zeros(n, np.float32))
+    expect(sb.SB_ERR_ARG, x0=-1.0)
+    bad_t = r.t.copy()
+    bad_t[0] = np.nan
+    expect(sb.SB_ERR_ARG, t=bad_t)
+    expect(sb.SB_ERR_ARG, t=np.zeros(300, np.float32), band=np.zeros(300, np.int32),
+           data=np.zeros(300, np.float32), sigma=np.ones(300, np.float32))
+    expect(sb.SB_ERR_ARG, t=np.zeros(0, np.float32), band=np.zeros(0, np.int32), data=np.zeros(0, np.float32),
+           sigma=np.ones(0, np.float32))
+    expect(sb.SB_ERR_ARG, z=0.95, band=np.zeros(n, np.int32))   # band 0 leaves the grid at z = 0.95
+    expect(sb.SB_ERR_BUDGET)                                     # 4 KiB budget < one request
+    ctx.close()
+
+
+def test_cancel(sb, model, bands6, requests):
+    ctx = sb.Context.from_model(model, bands6, hbm_budget_bytes=16 * 1024)
+    tks = [submit(ctx, it) for it in requests[:20]]
+    for tk in tks[5:15]:
+        ctx.fit_cancel(tk)
+    res = [ctx.fit_wait(tk, 60.0) for tk in tks]
+    st = ctx.stats()
+    ctx.close()
+    assert all(x is not None for x in res)
+    for i, x in enumerate(res):
+        if 5 <= i < 15:
+            assert x.status in (sb.SB_CANCELLED, sb.SB_OK)
+        else:
+            assert x.status == sb.SB_OK
+    assert sum(x.status == sb.SB_CANCELLED for x in res) >= 5
+    assert st["completed"] + st["cancelled"] == 20
+    with pytest.raises(sb.SaltBFError):
+        ctx2 = sb.Context.from_model(model, bands6)
+        try:
+            ctx2.fit_poll(12345)
+        finally:
+            ctx2.close()
+
+
+def test_poll_and_ticket_lifecycle(sb, model, bands6, requests):
+    ctx = sb.Context.from_model(model, bands6)
+    tk = submit(ctx, requests[3])
+    res = None
+    for _ in range(20000):
+        res = ctx.fit_poll(tk)
+        if res is not None:
+            break
+    if res is None:
+        res = ctx.fit_wait(tk, 30.0)
+    assert res is not None and res.status == sb.SB_OK
+    assert res.t_submit <= res.t_admit <= res.t_done
+    with pytest.raises(sb.SaltBFError) as e:
+        ctx.fit_poll(tk)          # a result is handed out once
+    assert e.value.status == sb.SB_ERR_NOTFOUND
+    ctx.close()
