@@ -44,8 +44,9 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
   const int tid = threadIdx.x;
   const bool chi2 = (b.flags & SB_OUT_CHI2) != 0;
   const float z = b.z[sn], t0 = b.t0[sn], x0 = b.x0[sn], x1 = b.x1[sn], c = b.c[sn];
-  const float s = 1.0f / (1.0f + z);
-  const float A = x0 * s;
+  const double s64 = 1.0 / (1.0 + (double)z);
+  const float s = (float)s64;
+  const float A = (float)((double)x0 * s64);
   const float qnan = __builtin_nanf("");
 
   int lo = 0, hi = b.n_obs;
@@ -60,11 +61,7 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
   }
   const size_t obase = BCAST ? (size_t)sn * (size_t)b.n_obs : 0;
 
-  if (tid < SB_MAX_BANDS) {
-    S.rlo[tid] = INT_MAX;
-    S.rhi[tid] = -1;
-  }
-  if (tid < 2) S.mask[tid] = 0u;
+  reset_scan(S.mask, S.rlo, S.rhi);
   __syncthreads();
 
   // acc: gradient (z, t0, x0, x1, c) and chi2
@@ -78,7 +75,7 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
   // scan: bands in use, rows touched; observations with nothing to integrate
   for (int i = lo + tid; i < hi; i += WG) {
     const int bd = b.band[i];
-    const PhaseCell pc = phase_cell(b.t[i], t0, s, m);
+    const PhaseCell pc = phase_cell(b.t[i], t0, s64, m);
     const bool bad_band = (unsigned)bd >= (unsigned)m.n_bands;
     if (bad_band || pc.nan) {
       if (bad_band) atomicOr(b.err, EFLAG_BAND);
@@ -103,19 +100,19 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
   }
   __syncthreads();
 
-  const unsigned masks[2] = {S.mask[0], S.mask[1]};
+  const unsigned masks[2] = {(unsigned)uni((int)S.mask[0]), (unsigned)uni((int)S.mask[1])};
   for (int h = 0; h < 2; ++h) {
     unsigned msk = masks[h];
     while (msk) {
       const int bd = h * 32 + __ffs(msk) - 1;
       msk &= msk - 1;
-      const int rlo = S.rlo[bd], rhi = S.rhi[bd];
-      const bool ok = band_rows<MODE>(m, tb, bd, s, c, x1, rlo, rhi, L, &S.flag);
+      const int rlo = uni(S.rlo[bd]), rhi = uni(S.rhi[bd]);
+      const bool ok = band_rows<MODE>(m, tb, bd, s64, c, x1, rlo, rhi, L, &S.flag);
       if (!ok && tid == 0) atomicOr(b.err, EFLAG_WINDOW);
       constexpr int NR = ModeInfo<MODE>::NR;
       for (int i = lo + tid; i < hi; i += WG) {
         if (b.band[i] != bd) continue;
-        const PhaseCell pc = phase_cell(b.t[i], t0, s, m);
+        const PhaseCell pc = phase_cell(b.t[i], t0, s64, m);
         if (!pc.in) continue;
         float f, dv[5];
         if (!ok) {
@@ -192,29 +189,12 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
   }
 }
 
-template <int MODE>
+template <int MODE, bool BCAST>
 __global__ __launch_bounds__(WG) void k_sn(KModel m, KTables tb, KBatch b) {
   extern __shared__ __align__(16) char smem[];
   __shared__ SnShared S;
   const Lds L = lds_carve<MODE>(smem, m, tb.max_pts);
-  sn_body<MODE, false>(m, tb, b, blockIdx.x, L, S);
-}
-
-// Persistent sweep: a fixed grid takes samples from a work counter until all
-// are done; every sample sees the whole observation table.
-template <int MODE>
-__global__ __launch_bounds__(WG) void k_sweep(KModel m, KTables tb, KBatch b) {
-  extern __shared__ __align__(16) char smem[];
-  __shared__ SnShared S;
-  const Lds L = lds_carve<MODE>(smem, m, tb.max_pts);
-  for (;;) {
-    if (threadIdx.x == 0) S.item = atomicAdd(b.counter, 1);
-    __syncthreads();
-    const int item = S.item;
-    __syncthreads();
-    if (item >= b.n_sn) break;
-    sn_body<MODE, true>(m, tb, b, item, L, S);
-  }
+  sn_body<MODE, BCAST>(m, tb, b, blockIdx.x, L, S);
 }
 
 size_t lds_bytes(const KModel& m, int max_pts, bool adj) {
@@ -228,41 +208,19 @@ static hipError_t prep_lds(K kern, size_t bytes) {
   return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-hipError_t launch_sn(bool adj, const KModel& m, const KTables& tb, const KBatch& b, hipStream_t st) {
-  const size_t lds = lds_bytes(m, tb.max_pts, adj);
-  hipError_t e;
-  if (adj) {
-    if ((e = prep_lds(k_sn<VJP>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sn<VJP>, dim3(b.n_sn), dim3(WG), lds, st, m, tb, b);
-  } else {
-    if ((e = prep_lds(k_sn<FWD>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sn<FWD>, dim3(b.n_sn), dim3(WG), lds, st, m, tb, b);
-  }
-  return hipGetLastError();
-}
-
-int sweep_blocks_per_cu(bool adj, const KModel& m, int max_pts) {
-  const size_t lds = lds_bytes(m, max_pts, adj);
-  int nb = 0;
-  hipError_t e = adj ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep<VJP>, WG, lds)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep<FWD>, WG, lds);
-  if (e != hipSuccess || nb < 1) nb = 1;
-  return nb;
-}
-
-hipError_t launch_sweep(bool adj, const KModel& m, const KTables& tb, const KBatch& b, int grid,
-                        hipStream_t st) {
-  const size_t lds = lds_bytes(m, tb.max_pts, adj);
-  hipError_t e = hipMemsetAsync(b.counter, 0, sizeof(int), st);
+template <int MODE, bool BCAST>
+static hipError_t launch_one(const KModel& m, const KTables& tb, const KBatch& b, hipStream_t st) {
+  const size_t lds = lds_layout_bytes<MODE>(m.n_phase, m.n_wave, tb.max_pts);
+  hipError_t e = prep_lds(k_sn<MODE, BCAST>, lds);
   if (e != hipSuccess) return e;
-  if (adj) {
-    if ((e = prep_lds(k_sweep<VJP>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sweep<VJP>, dim3(grid), dim3(WG), lds, st, m, tb, b);
-  } else {
-    if ((e = prep_lds(k_sweep<FWD>, lds)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sweep<FWD>, dim3(grid), dim3(WG), lds, st, m, tb, b);
-  }
+  hipLaunchKernelGGL((k_sn<MODE, BCAST>), dim3(b.n_sn), dim3(WG), lds, st, m, tb, b);
   return hipGetLastError();
+}
+
+hipError_t launch_sn(bool adj, const KModel& m, const KTables& tb, const KBatch& b, hipStream_t st) {
+  const bool bc = (b.flags & SB_OBS_BROADCAST) != 0;
+  if (adj) return bc ? launch_one<VJP, true>(m, tb, b, st) : launch_one<VJP, false>(m, tb, b, st);
+  return bc ? launch_one<FWD, true>(m, tb, b, st) : launch_one<FWD, false>(m, tb, b, st);
 }
 
 }  // namespace sbk

@@ -30,13 +30,10 @@ struct sb_ctx {
   float2* d_pts = nullptr;
   int* d_npts = nullptr;
   int* d_err = nullptr;
-  int* d_counters = nullptr;           // ring of sweep work counters
-  std::atomic<unsigned> next_counter{0};
   int n_bands = 0;
   int max_pts = 0;
   std::vector<double> band_lo, band_hi; // sample range of each band
   int n_cu = 1;
-  int sweep_bpc[2] = {0, 0};           // persistent blocks per CU (fwd, adj), 0 = not queried
   size_t max_lds = 65536;
   std::mutex mu;                       // band registration, server start
   sbh::Server* server = nullptr;
@@ -50,5 +47,3 @@ struct sb_ctx {
     return t;
   }
 };
-
-constexpr int SB_N_COUNTERS = 256;

@@ -11,13 +11,29 @@
 //     R(a)  = sum_j G(j) (M0 + x1 M1)[a, j]             (one row projection per row)
 //     f_i   = A * sum_a wp_a(p_i) R(a)                  (4 taps per observation)
 // This is the same sum as the definition, only reassociated.  The adjoint
-// needs three more weight vectors/projections (colour, wavelength derivative,
+// needs more weight vectors and projections (colour, wavelength derivative,
 // M1 alone), which reuse the same surface reads.
+//
+// Precision: storage, weights and every sum are FP32.  The grid coordinates
+// (s = 1/(1+z), the phase, the rest wavelengths mu_k) are formed in FP64 and
+// split into an integer cell and an FP32 fraction, so their rounding does not
+// move the evaluation point.  The wavelength derivative of the Catmull-Rom
+// interpolant is evaluated on first differences D(j) = M(j+1) - M(j) of the
+// nodes (exact in FP32 for neighbouring values), with the weights
+// e_t = -(dw_0 + ... + dw_t); the same derivative written with the derivative
+// weights dw_t directly would cancel column by column.
 #pragma once
 
 #include "sb_internal.h"
 
 namespace sbk {
+
+// A value every lane of the workgroup holds equally (read from LDS after a
+// barrier, or from a kernel argument), made visibly uniform to the compiler.
+// Every loop bound, early exit or branch that encloses a barrier goes through
+// it, so the compiler keeps those exits uniform and never splits a wave
+// around a barrier.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Which row projections a pass computes.
 //   FWD: Rx                       (flux)
@@ -25,10 +41,14 @@ namespace sbk {
 //   VJP: Rx, R1, Rc, Rl           (all five partials, including z)
 enum Mode { FWD = 0, FIT = 1, VJP = 2 };
 
+// NP per-point arrays, NG weight vectors, NR row projections.
+//   FWD: P                                   | G               | Rx
+//   FIT: P, Pc                               | G, Gc           | Rx, R1, Rc
+//   VJP: P, Pc, Plc (4 taps), Pd (3 taps)    | G, Gc, Glc, Gd  | Rx, R1, Rc, Rl
 template <int MODE> struct ModeInfo;
-template <> struct ModeInfo<FWD> { static constexpr int NG = 1, NR = 1; };
-template <> struct ModeInfo<FIT> { static constexpr int NG = 2, NR = 3; };
-template <> struct ModeInfo<VJP> { static constexpr int NG = 3, NR = 4; };
+template <> struct ModeInfo<FWD> { static constexpr int NP = 4, NG = 1, NR = 1; };
+template <> struct ModeInfo<FIT> { static constexpr int NP = 8, NG = 2, NR = 3; };
+template <> struct ModeInfo<VJP> { static constexpr int NP = 15, NG = 4, NR = 4; };
 
 // Catmull-Rom (Keys a = -1/2) weights of the four nodes a-1..a+2 at fraction x of
 // cell a; linear weights (nodes a, a+1 only) in the first and last cell.
@@ -57,8 +77,23 @@ __device__ inline void cr_dweights(float x, bool edge, float d[4]) {
   d[3] = 1.5f * x2 - x;
 }
 
-// Phase cell of an observation.  Written with contraction off so that every
-// call site rounds identically (row ranges and weights must agree).
+// The same derivative on first differences: sum_t dw_t M(a-1+t) equals
+// sum_{t<3} e_t D(a-1+t) with D(j) = M(j+1) - M(j) and e_t = -(dw_0 + .. + dw_t).
+// Edge cells (linear): the derivative is D(a).
+__device__ inline void cr_diff_weights(float x, bool edge, float e[3]) {
+  if (edge) {
+    e[0] = 0.f; e[1] = 1.f; e[2] = 0.f;
+    return;
+  }
+  const float x2 = x * x;
+  e[0] = 1.5f * x2 - 2.f * x + 0.5f;
+  e[1] = -3.f * x2 + 3.f * x + 0.5f;
+  e[2] = 1.5f * x2 - x;
+}
+
+// Phase cell of an observation, from FP64 coordinates.  Written with
+// contraction off so that every call site rounds identically (row ranges and
+// weights must agree).
 struct PhaseCell {
   float p;      // rest phase (t - t0) s
   float x;      // fraction in cell a
@@ -69,17 +104,19 @@ struct PhaseCell {
   int r0, r1;   // rows with non-zero weight
 };
 
-__device__ inline PhaseCell phase_cell(float t, float t0, float s, const KModel& m) {
+__device__ inline PhaseCell phase_cell(float t, float t0, double s, const KModel& m) {
 #pragma clang fp contract(off)
   PhaseCell c;
-  c.p = (t - t0) * s;
-  const float u = (c.p - m.phase0) * m.inv_dphase;
+  const double p = ((double)t - (double)t0) * s;
+  const double u = (p - m.phase0_d) * m.inv_dphase_d;
+  c.p = (float)p;
   c.nan = !(u == u);
-  c.in = (u >= 0.f) && (u <= (float)(m.n_phase - 1));
-  int a = (int)floorf(c.in ? u : 0.f);
+  c.in = (u >= 0.0) && (u <= (double)(m.n_phase - 1));
+  const double uu = c.in ? u : 0.0;
+  int a = (int)floor(uu);
   a = a < 0 ? 0 : (a > m.n_phase - 2 ? m.n_phase - 2 : a);
   c.a = a;
-  c.x = (c.in ? u : 0.f) - (float)a;
+  c.x = (float)(uu - (double)a);
   c.edge = (a == 0) || (a == m.n_phase - 2);
   c.r0 = c.edge ? a : a - 1;
   c.r1 = c.edge ? a + 1 : a + 2;
@@ -100,7 +137,7 @@ __device__ inline void colour_law(float mu, const KModel& m, float& cl, float& d
 
 // Pointers into the dynamic LDS of one workgroup.
 struct Lds {
-  float* P;    // [NG][4][max_pts]   point weights per tap
+  float* P;    // [NP][max_pts]      point weights per tap
   int* j0;     // [max_pts]          wavelength cell per point
   int* kf;     // [n_wave + 2]       first point of each cell
   float* G;    // [NG][n_wave + 4]   weight vectors over the window
@@ -111,9 +148,9 @@ struct Lds {
 
 template <int MODE>
 __host__ __device__ inline size_t lds_layout_bytes(int n_phase, int n_wave, int max_pts) {
-  constexpr int NG = ModeInfo<MODE>::NG, NR = ModeInfo<MODE>::NR;
+  constexpr int NP = ModeInfo<MODE>::NP, NG = ModeInfo<MODE>::NG, NR = ModeInfo<MODE>::NR;
   size_t b = 0;
-  b += (size_t)NG * 4 * max_pts * sizeof(float);
+  b += (size_t)NP * max_pts * sizeof(float);
   b += (size_t)max_pts * sizeof(int);
   b += (size_t)(n_wave + 2) * sizeof(int);
   b += (size_t)NG * (n_wave + 4) * sizeof(float);
@@ -124,10 +161,10 @@ __host__ __device__ inline size_t lds_layout_bytes(int n_phase, int n_wave, int 
 
 template <int MODE>
 __device__ inline Lds lds_carve(char* base, const KModel& m, int max_pts) {
-  constexpr int NG = ModeInfo<MODE>::NG, NR = ModeInfo<MODE>::NR;
+  constexpr int NP = ModeInfo<MODE>::NP, NG = ModeInfo<MODE>::NG, NR = ModeInfo<MODE>::NR;
   Lds L;
   char* p = base;
-  L.P = (float*)p;  p += (size_t)NG * 4 * max_pts * sizeof(float);
+  L.P = (float*)p;  p += (size_t)NP * max_pts * sizeof(float);
   L.j0 = (int*)p;   p += (size_t)max_pts * sizeof(int);
   L.kf = (int*)p;   p += (size_t)(m.n_wave + 2) * sizeof(int);
   L.G = (float*)p;  p += (size_t)NG * (m.n_wave + 4) * sizeof(float);
@@ -139,21 +176,27 @@ __device__ inline Lds lds_carve(char* base, const KModel& m, int max_pts) {
 
 // Row projections of one (supernova, band) for rows [rlo, rhi]:
 //   R[(a - rlo)*NR + 0] = sum_j G(j)  (M0 + x1 M1)[a, j]
-//   R[...+1]            = sum_j G(j)  M1[a, j]                (FIT, VJP)
-//   R[...+2]            = sum_j Gc(j) (M0 + x1 M1)[a, j]      (FIT, VJP)
-//   R[...+3]            = sum_j Gl(j) (M0 + x1 M1)[a, j]      (VJP)
-// with G(j)  = sum_k om_k wl_j(mu_k),  om_k = W_k exp(c CL(mu_k)),
-//      Gc(j) = sum_k om_k CL(mu_k) wl_j(mu_k),
-//      Gl(j) = sum_k om_k mu_k [wl_j'(mu_k) + c CL'(mu_k) wl_j(mu_k)].
+//   R[...+1]            = sum_j G(j)  M1[a, j]                          (FIT, VJP)
+//   R[...+2]            = sum_j Gc(j) (M0 + x1 M1)[a, j]                (FIT, VJP)
+//   R[...+3]            = sum_j Glc(j) (M0 + x1 M1)[a, j]
+//                       + sum_j Gd(j) (D0 + x1 D1)[a, j]                (VJP)
+// with om_k = W_k exp(c CL(mu_k)) and
+//   G(j)   = sum_k om_k wl_j(mu_k),          Gc(j) = sum_k om_k CL(mu_k) wl_j(mu_k),
+//   Glc(j) = sum_k om_k mu_k c CL'(mu_k) wl_j(mu_k),
+//   Gd(j)  = sum_k om_k mu_k e_j(mu_k) / dwave   (difference weights, D(j) = M(j+1) - M(j)),
+// so that Rl gives sum_k om_k mu_k [dI/dmu + c CL' I] at the phase rows.
 // All threads of the workgroup must call it (it holds barriers).  Returns
 // false, uniformly, when the band's rest window leaves the wavelength grid.
 // *flag is an LDS int used as scratch.
 template <int MODE>
-__device__ bool band_rows(const KModel& m, const KTables& tb, int bd, float s, float c, float x1,
+__device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, float c, float x1,
                           int rlo, int rhi, const Lds& L, int* flag) {
   constexpr int NG = ModeInfo<MODE>::NG, NR = ModeInfo<MODE>::NR;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int np = tb.npts[bd];
+  const int np = uni(tb.npts[bd]);
+  bd = uni(bd);
+  rlo = uni(rlo);
+  rhi = uni(rhi);
   const float2* pts = tb.pts + (size_t)bd * SB_MAX_BAND_POINTS;
   const int P = tb.max_pts;
 
@@ -163,13 +206,21 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, float s, f
   // (1) quadrature points: wavelength cell, tap weights times om_k
   for (int k = tid; k < np; k += WG) {
     const float2 lw = pts[k];
-    const float mu = lw.x * s;
-    const float v = (mu - m.wave0) * m.inv_dwave;
-    const bool ok = (v >= 0.f) && (v <= (float)(m.n_wave - 1));
+    float x, mu;
+    int j0;
+    bool ok;
+    {
+#pragma clang fp contract(off)
+      const double mu_d = (double)lw.x * s;
+      const double v = (mu_d - m.wave0_d) * m.inv_dwave_d;
+      ok = (v >= 0.0) && (v <= (double)(m.n_wave - 1));
+      const double vv = ok ? v : 0.0;
+      j0 = (int)floor(vv);
+      j0 = j0 < 0 ? 0 : (j0 > m.n_wave - 2 ? m.n_wave - 2 : j0);
+      x = (float)(vv - (double)j0);
+      mu = (float)mu_d;
+    }
     if (!ok) *flag = 1;
-    int j0 = (int)floorf(ok ? v : 0.f);
-    j0 = j0 < 0 ? 0 : (j0 > m.n_wave - 2 ? m.n_wave - 2 : j0);
-    const float x = (ok ? v : 0.f) - (float)j0;
     const bool edge = (j0 == 0) || (j0 == m.n_wave - 2);
     float cl, dcl;
     colour_law(mu, m, cl, dcl);
@@ -184,23 +235,26 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, float s, f
       for (int t = 0; t < 4; ++t) L.P[(4 + t) * P + k] = omc * w[t];
     }
     if (MODE == VJP) {
-      float d[4];
-      cr_dweights(x, edge, d);
+      float e[3];
+      cr_diff_weights(x, edge, e);
       const float omu = om * mu;
-      const float ccl = c * dcl;
+      const float omlc = omu * (c * dcl);
+      const float omd = omu * m.inv_dwave;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) L.P[(8 + t) * P + k] = omu * fmaf(d[t], m.inv_dwave, ccl * w[t]);
+      for (int t = 0; t < 4; ++t) L.P[(8 + t) * P + k] = omlc * w[t];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) L.P[(12 + t) * P + k] = omd * e[t];
     }
     L.j0[k] = j0;
   }
   __syncthreads();
-  if (*flag) return false;
+  if (uni(*flag)) return false;
 
   // (2) first point of every wavelength cell touched (cells are non-decreasing in k)
-  const int j0f = L.j0[0], j0l = L.j0[np - 1];
+  const int j0f = uni(L.j0[0]), j0l = uni(L.j0[np - 1]);
   const int ncell = j0l - j0f + 1;
   for (int k = tid; k < np; k += WG) {
-    // cells are non-decreasing in k; the clamps only keep every index in bounds
+    // the clamps only keep every index in bounds
     const int cur = min(max(L.j0[k] - j0f, 0), ncell - 1);
     const int prev = (k == 0) ? -1 : min(max(L.j0[k - 1] - j0f, -1), ncell - 1);
     for (int q = prev + 1; q <= cur; ++q) L.kf[q] = k;
@@ -208,7 +262,8 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, float s, f
   if (tid == 0) L.kf[ncell] = np;
   __syncthreads();
 
-  // (3) weight vectors over the window of columns [j_lo, j_hi]
+  // (3) weight vectors over the window of columns [j_lo, j_hi]; node tap t and
+  //     difference tap t of a point in cell j0 both land on column j0 - 1 + t
   const int j_lo = j0f - 1 < 0 ? 0 : j0f - 1;
   const int j_hi = j0l + 2 > m.n_wave - 1 ? m.n_wave - 1 : j0l + 2;
   const int J = j_hi - j_lo + 1;
@@ -223,8 +278,12 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, float s, f
       if (q < 0 || q >= ncell) continue;
       const int k1 = min(L.kf[q + 1], np);
       for (int k = max(L.kf[q], 0); k < k1; ++k) {
-#pragma unroll
-        for (int h = 0; h < NG; ++h) g[h] += L.P[(4 * h + t) * P + k];
+        g[0] += L.P[t * P + k];
+        if (MODE != FWD) g[1] += L.P[(4 + t) * P + k];
+        if (MODE == VJP) {
+          g[2] += L.P[(8 + t) * P + k];
+          if (t < 3) g[3] += L.P[(12 + t) * P + k];
+        }
       }
     }
 #pragma unroll
@@ -239,37 +298,53 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, float s, f
   for (int rb = 0; rb < nrow; rb += 64) {
     const int a = rlo + rb + lane;
     const int a_ld = a < m.n_phase - 1 ? a : m.n_phase - 1;
-    const float2* colp = tb.surf + (size_t)(j_lo + c0) * m.row_pad + a_ld;
-    float acc[4];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = 0.f;
-    int cc = c0;
-    for (; cc + 4 <= c1; cc += 4) {
-      float2 mm[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) mm[u] = colp[(size_t)(cc - c0 + u) * m.row_pad];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const float g = L.G[cc + u];
-        const float mx = fmaf(x1, mm[u].y, mm[u].x);
+    const float2* colp = tb.surf + a_ld;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    if (MODE == VJP) {
+      // carries the next column for the first differences (clamped at the grid end,
+      // where its difference weight is zero)
+      float2 cur = colp[(size_t)min(j_lo + c0, m.n_wave - 1) * m.row_pad];
+#pragma unroll 4
+      for (int cc = c0; cc < c1; ++cc) {
+        const float2 nxt = colp[(size_t)min(j_lo + cc + 1, m.n_wave - 1) * m.row_pad];
+        const float mx = fmaf(x1, cur.y, cur.x);
+        const float dx = fmaf(x1, nxt.y - cur.y, nxt.x - cur.x);
+        const float g = L.G[cc];
         acc[0] = fmaf(g, mx, acc[0]);
-        if (MODE != FWD) {
-          acc[1] = fmaf(g, mm[u].y, acc[1]);
-          acc[2] = fmaf(L.G[L.gstride + cc + u], mx, acc[2]);
-        }
-        if (MODE == VJP) acc[3] = fmaf(L.G[2 * L.gstride + cc + u], mx, acc[3]);
-      }
-    }
-    for (; cc < c1; ++cc) {
-      const float2 mm = colp[(size_t)(cc - c0) * m.row_pad];
-      const float g = L.G[cc];
-      const float mx = fmaf(x1, mm.y, mm.x);
-      acc[0] = fmaf(g, mx, acc[0]);
-      if (MODE != FWD) {
-        acc[1] = fmaf(g, mm.y, acc[1]);
+        acc[1] = fmaf(g, cur.y, acc[1]);
         acc[2] = fmaf(L.G[L.gstride + cc], mx, acc[2]);
+        acc[3] = fmaf(L.G[2 * L.gstride + cc], mx, acc[3]);
+        acc[3] = fmaf(L.G[3 * L.gstride + cc], dx, acc[3]);
+        cur = nxt;
       }
-      if (MODE == VJP) acc[3] = fmaf(L.G[2 * L.gstride + cc], mx, acc[3]);
+    } else {
+      const float2* cp = colp + (size_t)(j_lo + c0) * m.row_pad;
+      int cc = c0;
+      for (; cc + 4 <= c1; cc += 4) {
+        float2 mm[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) mm[u] = cp[(size_t)(cc - c0 + u) * m.row_pad];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float g = L.G[cc + u];
+          const float mx = fmaf(x1, mm[u].y, mm[u].x);
+          acc[0] = fmaf(g, mx, acc[0]);
+          if (MODE == FIT) {
+            acc[1] = fmaf(g, mm[u].y, acc[1]);
+            acc[2] = fmaf(L.G[L.gstride + cc + u], mx, acc[2]);
+          }
+        }
+      }
+      for (; cc < c1; ++cc) {
+        const float2 mm = cp[(size_t)(cc - c0) * m.row_pad];
+        const float g = L.G[cc];
+        const float mx = fmaf(x1, mm.y, mm.x);
+        acc[0] = fmaf(g, mx, acc[0]);
+        if (MODE == FIT) {
+          acc[1] = fmaf(g, mm.y, acc[1]);
+          acc[2] = fmaf(L.G[L.gstride + cc], mx, acc[2]);
+        }
+      }
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) L.RP[(wv * 64 + lane) * NR + r] = acc[r];
@@ -293,7 +368,8 @@ __device__ inline int row_index(int a, int rlo, int rhi) {
   return min(max(a, rlo), rhi) - rlo;
 }
 
-// Sum of N values over the workgroup in a fixed order; the result is valid in thread 0.
+// Sum of N values over the workgroup in a fixed order; every thread gets the
+// same result (each thread adds the four per-wave partials in wave order).
 template <int N>
 __device__ inline void block_sum(float (&v)[N], float* red) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -309,15 +385,23 @@ __device__ inline void block_sum(float (&v)[N], float* red) {
     for (int q = 0; q < N; ++q) red[wv * N + q] = v[q];
   }
   __syncthreads();
-  if (tid == 0) {
 #pragma unroll
-    for (int q = 0; q < N; ++q) {
-      float x = red[q];
-      for (int w2 = 1; w2 < NWAVES; ++w2) x += red[w2 * N + q];
-      v[q] = x;
-    }
+  for (int q = 0; q < N; ++q) {
+    float x = red[q];
+#pragma unroll
+    for (int w2 = 1; w2 < NWAVES; ++w2) x += red[w2 * N + q];
+    v[q] = x;
   }
   __syncthreads();
+}
+
+// Branch-free reset of the per-band scan state (every thread stores the same
+// values), so no lane-dependent branch sits in loops that hold barriers.
+__device__ inline void reset_scan(unsigned* mask, int* rlo, int* rhi) {
+  const int tid = threadIdx.x;
+  rlo[tid & (SB_MAX_BANDS - 1)] = 0x7fffffff;
+  rhi[tid & (SB_MAX_BANDS - 1)] = -1;
+  mask[tid & 1] = 0u;
 }
 
 }  // namespace sbk

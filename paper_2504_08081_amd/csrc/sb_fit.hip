@@ -5,10 +5,12 @@
 // sb_device.h in FIT mode (row projections for the flux, d/dx1 and d/dc; d/dt0
 // comes from the phase-weight derivatives and d/d ln x0 equals the flux), and
 // accumulates chi2, J^T W J and J^T W r over the fit's observations with a
-// fixed-order workgroup reduction.  Thread 0 does the 4x4 damped solve.  The
-// fit's state is read from and written back to its slot, so a fit gives the
-// same result however its iterations are split over launches and whichever
-// other fits share the launch.
+// fixed-order workgroup reduction whose result every thread receives.  Every
+// thread then holds an identical copy of the LM state and takes the same 4x4
+// damped step, so the iteration loop has no thread-dependent branch around its
+// barriers.  The fit's state is read from and written back to its slot, so a
+// fit gives the same result however its iterations are split over launches and
+// whichever other fits share the launch.
 #include <climits>
 
 #include "sb_device.h"
@@ -20,15 +22,10 @@ struct FitShared {
   int rlo[SB_MAX_BANDS];
   int rhi[SB_MAX_BANDS];
   int flag;
-  int skip;
   float red[NWAVES * 16];
-  float q[4], qt[4];
-  float lambda, chi2;
-  float H[10], g[4];
-  int iter, n_accept, status;
 };
 
-// chi2, H (packed) and g at parameters q = (t0, ln x0, x1, c); valid in thread 0.
+// chi2, H (packed) and g at parameters q = (t0, ln x0, x1, c); every thread gets them.
 struct FitObs {
   const float* t;
   const int* band;
@@ -37,22 +34,19 @@ struct FitObs {
   int n;
 };
 
-__device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, const FitObs& O, float s,
+__device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, const FitObs& O, double s64,
                          const float* q, const Lds& L, FitShared& S, float (&out)[15]) {
   const int tid = threadIdx.x;
   const float t0 = q[0], x0 = expf(q[1]), x1 = q[2], c = q[3];
-  const float A = x0 * s;
-  if (tid < SB_MAX_BANDS) {
-    S.rlo[tid] = INT_MAX;
-    S.rhi[tid] = -1;
-  }
-  if (tid < 2) S.mask[tid] = 0u;
+  const float s = (float)s64;
+  const float A = (float)((double)x0 * s64);
+  reset_scan(S.mask, S.rlo, S.rhi);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 15; ++k) out[k] = 0.f;
   for (int i = tid; i < O.n; i += WG) {
     const int bd = O.band[i];
-    const PhaseCell pc = phase_cell(O.t[i], t0, s, m);
+    const PhaseCell pc = phase_cell(O.t[i], t0, s64, m);
     if (!pc.in || pc.nan || (unsigned)bd >= (unsigned)m.n_bands) {
       const float r = O.data[i];
       out[14] = fmaf(r * r, O.w[i], out[14]);
@@ -63,19 +57,19 @@ __device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, cons
     atomicOr(&S.mask[bd >> 5], 1u << (bd & 31));
   }
   __syncthreads();
-  const unsigned masks[2] = {S.mask[0], S.mask[1]};
+  const unsigned masks[2] = {(unsigned)uni((int)S.mask[0]), (unsigned)uni((int)S.mask[1])};
   constexpr int NR = ModeInfo<FIT>::NR;
   for (int h = 0; h < 2; ++h) {
     unsigned msk = masks[h];
     while (msk) {
       const int bd = h * 32 + __ffs(msk) - 1;
       msk &= msk - 1;
-      const int rlo = S.rlo[bd], rhi = S.rhi[bd];
-      const bool ok = band_rows<FIT>(m, tb, bd, s, c, x1, rlo, rhi, L, &S.flag);
+      const int rlo = uni(S.rlo[bd]), rhi = uni(S.rhi[bd]);
+      const bool ok = band_rows<FIT>(m, tb, bd, s64, c, x1, rlo, rhi, L, &S.flag);
       if (!ok && tid == 0) atomicOr(F.err, EFLAG_WINDOW);
       for (int i = tid; i < O.n; i += WG) {
         if (O.band[i] != bd) continue;
-        const PhaseCell pc = phase_cell(O.t[i], t0, s, m);
+        const PhaseCell pc = phase_cell(O.t[i], t0, s64, m);
         if (!pc.in || pc.nan) continue;
         float J[4], f;
         if (!ok) {
@@ -121,8 +115,7 @@ __device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, cons
   block_sum<15>(out, S.red);
 }
 
-// Solve (H + lambda diag H) d = g by Cholesky (thread 0).  False if a pivot is
-// not positive.
+// Solve (H + lambda diag H) d = g by Cholesky.  False if a pivot is not positive.
 __device__ bool damped_solve(const float* H, const float* g, float lambda, float* d) {
   float a[4][4];
   int k = 0;
@@ -168,9 +161,12 @@ __global__ __launch_bounds__(WG) void k_fit(KModel m, KTables tb, KFit F) {
   const Lds L = lds_carve<FIT>(smem, m, tb.max_pts);
   const int tid = threadIdx.x;
   FitSlot* sl = F.slots + F.active[blockIdx.x];
-  const int adm = F.admit[blockIdx.x];
+  const int adm = uni(F.admit[blockIdx.x]);
   FitObs O;
   float z;
+  // the LM state; every thread holds the same values
+  float q[4], H[10], g[4], lambda, chi2;
+  int iter, n_acc, status;
   if (adm >= 0) {
     // first launch of this fit: move its observations from the inbox to the arena
     const AdmitHeader h = F.hdr[adm];
@@ -180,22 +176,6 @@ __global__ __launch_bounds__(WG) void k_fit(KModel m, KTables tb, KFit F) {
       F.data[h.arena_off + i] = F.in_data[h.src_off + i];
       F.w[h.arena_off + i] = F.in_w[h.src_off + i];
     }
-    if (tid == 0) {
-      sl->obs_off = h.arena_off;
-      sl->n_obs = h.n_obs;
-      sl->iter = -1;
-      sl->n_accept = 0;
-      sl->status = SB_OK;
-      sl->z = h.z;
-      sl->q[0] = h.t0;
-      sl->q[1] = h.lnx0;
-      sl->q[2] = h.x1;
-      sl->q[3] = h.c;
-      sl->lambda = F.lambda0;
-      sl->chi2 = 0.f;
-      for (int k = 0; k < 10; ++k) sl->H[k] = 0.f;
-      for (int k = 0; k < 4; ++k) sl->g[k] = 0.f;
-    }
     // this launch reads the inbox copy; the arena copy serves the later launches
     O.t = F.in_t + h.src_off;
     O.band = F.in_band + h.src_off;
@@ -203,6 +183,19 @@ __global__ __launch_bounds__(WG) void k_fit(KModel m, KTables tb, KFit F) {
     O.w = F.in_w + h.src_off;
     O.n = h.n_obs;
     z = h.z;
+    q[0] = h.t0;
+    q[1] = h.lnx0;
+    q[2] = h.x1;
+    q[3] = h.c;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) H[k] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g[k] = 0.f;
+    lambda = F.lambda0;
+    chi2 = 0.f;
+    iter = -1;
+    n_acc = 0;
+    status = SB_OK;
   } else {
     O.t = F.t + sl->obs_off;
     O.band = F.band + sl->obs_off;
@@ -210,98 +203,80 @@ __global__ __launch_bounds__(WG) void k_fit(KModel m, KTables tb, KFit F) {
     O.w = F.w + sl->obs_off;
     O.n = sl->n_obs;
     z = sl->z;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = sl->q[k];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) H[k] = sl->H[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g[k] = sl->g[k];
+    lambda = sl->lambda;
+    chi2 = sl->chi2;
+    iter = sl->iter;
+    n_acc = sl->n_accept;
+    status = sl->status;
   }
-  const float s = 1.0f / (1.0f + z);
-  if (tid == 0 && adm >= 0) {
-    const AdmitHeader h = F.hdr[adm];
-    S.q[0] = h.t0;
-    S.q[1] = h.lnx0;
-    S.q[2] = h.x1;
-    S.q[3] = h.c;
-    for (int k = 0; k < 10; ++k) S.H[k] = 0.f;
-    for (int k = 0; k < 4; ++k) S.g[k] = 0.f;
-    S.lambda = F.lambda0;
-    S.chi2 = 0.f;
-    S.iter = -1;
-    S.n_accept = 0;
-    S.status = SB_OK;
-  } else if (tid == 0) {
-    for (int k = 0; k < 4; ++k) S.q[k] = sl->q[k];
-    for (int k = 0; k < 10; ++k) S.H[k] = sl->H[k];
-    for (int k = 0; k < 4; ++k) S.g[k] = sl->g[k];
-    S.lambda = sl->lambda;
-    S.chi2 = sl->chi2;
-    S.iter = sl->iter;
-    S.n_accept = sl->n_accept;
-    S.status = sl->status;
-  }
-  __syncthreads();
+  const double s64 = 1.0 / (1.0 + (double)z);
   float out[15];
-  const bool first = S.iter < 0;
-  __syncthreads();
-  if (first) {
-    fit_eval(m, tb, F, O, s, S.q, L, S, out);
-    if (tid == 0) {
-      if (isfinite(out[14])) {
-        for (int k = 0; k < 10; ++k) S.H[k] = out[k];
-        for (int k = 0; k < 4; ++k) S.g[k] = out[10 + k];
-        S.chi2 = out[14];
-        S.iter = 0;
-        S.lambda = F.lambda0;
-      } else {
-        S.chi2 = out[14];
-        S.status = SB_FIT_DIVERGED;
-      }
+  if (uni(iter < 0 ? 1 : 0)) {
+    fit_eval(m, tb, F, O, s64, q, L, S, out);
+    if (uni(isfinite(out[14]) ? 1 : 0)) {
+#pragma unroll
+      for (int k = 0; k < 10; ++k) H[k] = out[k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) g[k] = out[10 + k];
+      chi2 = out[14];
+      iter = 0;
+      lambda = F.lambda0;
+    } else {
+      chi2 = out[14];
+      status = SB_FIT_DIVERGED;
     }
-    __syncthreads();
   }
   for (int it = 0; it < F.iters; ++it) {
-    // every thread reads the loop state before thread 0 may change it
-    const bool done = (S.status != SB_OK) || (S.iter >= F.fit_iters);
-    __syncthreads();
-    if (done) break;
-    if (tid == 0) {
-      float d[4];
-      if (damped_solve(S.H, S.g, S.lambda, d)) {
-        for (int k = 0; k < 4; ++k) S.qt[k] = S.q[k] + d[k];
-        S.skip = 0;
-      } else {
-        S.lambda = fminf(S.lambda * 10.f, 1e9f);
-        S.iter += 1;
-        S.skip = 1;
-      }
+    if (uni((status != SB_OK || iter >= F.fit_iters) ? 1 : 0)) break;
+    float d[4];
+    const int solved = uni(damped_solve(H, g, lambda, d) ? 1 : 0);
+    if (!solved) {
+      lambda = fminf(lambda * 10.f, 1e9f);
+      iter += 1;
+      continue;
     }
-    __syncthreads();
-    const int skip = S.skip;
-    __syncthreads();
-    if (skip) continue;
-    fit_eval(m, tb, F, O, s, S.qt, L, S, out);
-    if (tid == 0) {
-      if (isfinite(out[14]) && out[14] < S.chi2) {
-        for (int k = 0; k < 4; ++k) S.q[k] = S.qt[k];
-        for (int k = 0; k < 10; ++k) S.H[k] = out[k];
-        for (int k = 0; k < 4; ++k) S.g[k] = out[10 + k];
-        S.chi2 = out[14];
-        S.lambda = fmaxf(S.lambda * 0.1f, 1e-9f);
-        S.n_accept += 1;
-      } else {
-        S.lambda = fminf(S.lambda * 10.f, 1e9f);
-      }
-      S.iter += 1;
+    float qt[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qt[k] = q[k] + d[k];
+    fit_eval(m, tb, F, O, s64, qt, L, S, out);
+    if (uni((isfinite(out[14]) && out[14] < chi2) ? 1 : 0)) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) q[k] = qt[k];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) H[k] = out[k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) g[k] = out[10 + k];
+      chi2 = out[14];
+      lambda = fmaxf(lambda * 0.1f, 1e-9f);
+      n_acc += 1;
+    } else {
+      lambda = fminf(lambda * 10.f, 1e9f);
     }
-    __syncthreads();
+    iter += 1;
   }
   if (tid == 0) {
-    for (int k = 0; k < 4; ++k) sl->q[k] = S.q[k];
-    for (int k = 0; k < 10; ++k) sl->H[k] = S.H[k];
-    for (int k = 0; k < 4; ++k) sl->g[k] = S.g[k];
-    sl->lambda = S.lambda;
-    sl->chi2 = S.chi2;
-    sl->iter = S.iter;
-    sl->n_accept = S.n_accept;
-    sl->status = S.status;
+    FitSlot st;
+    st.obs_off = adm >= 0 ? F.hdr[adm].arena_off : sl->obs_off;
+    st.n_obs = O.n;
+    st.iter = iter;
+    st.n_accept = n_acc;
+    st.status = status;
+    st.pad_[0] = st.pad_[1] = st.pad_[2] = 0;
+    st.z = z;
+    for (int k = 0; k < 4; ++k) st.q[k] = q[k];
+    st.lambda = lambda;
+    st.chi2 = chi2;
+    for (int k = 0; k < 10; ++k) st.H[k] = H[k];
+    for (int k = 0; k < 4; ++k) st.g[k] = g[k];
+    *sl = st;
     const int oi = F.out_idx[blockIdx.x];
-    if (oi >= 0) F.results[oi] = *sl;
+    if (oi >= 0) F.results[oi] = st;
   }
 }
 

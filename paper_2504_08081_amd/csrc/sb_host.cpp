@@ -128,7 +128,6 @@ static void free_ctx(sb_ctx* c) {
   if (c->d_pts) (void)hipFree(c->d_pts);
   if (c->d_npts) (void)hipFree(c->d_npts);
   if (c->d_err) (void)hipFree(c->d_err);
-  if (c->d_counters) (void)hipFree(c->d_counters);
   delete c;
 }
 
@@ -182,6 +181,10 @@ sb_status sb_create(const sb_model_desc* md, const sb_config* cfg_in, int device
   k.inv_dphase = (float)(1.0 / md->dphase);
   k.wave0 = (float)md->wave0;
   k.inv_dwave = (float)(1.0 / md->dwave);
+  k.phase0_d = md->phase0;
+  k.inv_dphase_d = 1.0 / md->dphase;
+  k.wave0_d = md->wave0;
+  k.inv_dwave_d = 1.0 / md->dwave;
   k.cl_b = (float)md->cl_wave_b;
   k.cl_inv_span = (float)(1.0 / (md->cl_wave_v - md->cl_wave_b));
   k.cl_deg = md->cl_degree;
@@ -203,16 +206,14 @@ sb_status sb_create(const sb_model_desc* md, const sb_config* cfg_in, int device
   if ((e = hipMalloc(&c->d_surf, surf.size() * sizeof(float2))) != hipSuccess ||
       (e = hipMalloc(&c->d_pts, pts_bytes)) != hipSuccess ||
       (e = hipMalloc(&c->d_npts, SB_MAX_BANDS * sizeof(int))) != hipSuccess ||
-      (e = hipMalloc(&c->d_err, sizeof(int))) != hipSuccess ||
-      (e = hipMalloc(&c->d_counters, SB_N_COUNTERS * sizeof(int))) != hipSuccess) {
+      (e = hipMalloc(&c->d_err, sizeof(int))) != hipSuccess) {
     free_ctx(c);
     return set_error(SB_ERR_NOMEM, std::string("sb_create: hipMalloc: ") + hipGetErrorString(e));
   }
   if ((e = hipMemcpy(c->d_surf, surf.data(), surf.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemset(c->d_pts, 0, pts_bytes)) != hipSuccess ||
       (e = hipMemset(c->d_npts, 0, SB_MAX_BANDS * sizeof(int))) != hipSuccess ||
-      (e = hipMemset(c->d_err, 0, sizeof(int))) != hipSuccess ||
-      (e = hipMemset(c->d_counters, 0, SB_N_COUNTERS * sizeof(int))) != hipSuccess) {
+      (e = hipMemset(c->d_err, 0, sizeof(int))) != hipSuccess) {
     free_ctx(c);
     return hip_fail(e, "sb_create: upload");
   }
@@ -258,7 +259,6 @@ sb_status sb_add_band(sb_ctx* ctx, const double* wave, const double* trans, int3
   ctx->max_pts = std::max(ctx->max_pts, np);
   ctx->n_bands = id + 1;
   ctx->km.n_bands = ctx->n_bands;
-  ctx->sweep_bpc[0] = ctx->sweep_bpc[1] = 0;
   *band_id = id;
   return SB_OK;
 }
@@ -267,8 +267,9 @@ static sb_status check_batch(const sb_ctx* ctx, const sb_batch* b, const char* w
   const std::string w(who);
   if (!ctx || !b) return set_error(SB_ERR_ARG, w + ": NULL argument");
   if (b->n_sn < 0 || b->n_obs < 0) return set_error(SB_ERR_ARG, w + ": negative size");
-  if (!(b->flags & SB_OBS_BROADCAST) && b->n_sn > (1 << 24) - 1)
-    return set_error(SB_ERR_ARG, w + ": more than 2^24 - 1 supernovae in one call");
+  if (b->n_sn > (1 << 24) - 1) return set_error(SB_ERR_ARG, w + ": more than 2^24 - 1 supernovae in one call");
+  if ((b->flags & SB_OBS_BROADCAST) && (int64_t)b->n_sn * b->n_obs > ((int64_t)1 << 40))
+    return set_error(SB_ERR_ARG, w + ": broadcast output too large");
   if (b->flags & ~(SB_OBS_BROADCAST | SB_OUT_CHI2)) return set_error(SB_ERR_ARG, w + ": unknown flags");
   if (ctx->n_bands == 0) return set_error(SB_ERR_STATE, w + ": no band registered");
   if (b->n_sn > 0 && (!b->z || !b->t0 || !b->x0 || !b->x1 || !b->c))
@@ -298,19 +299,7 @@ static sb_status launch(sb_ctx* ctx, bool adj, sbk::KBatch& kb, hipStream_t st) 
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   const size_t lds = sbk::lds_bytes(ctx->km, ctx->max_pts, adj);
   if (lds > ctx->max_lds) return set_error(SB_ERR_ARG, "bands too large for LDS");
-  const sbk::KTables tb = ctx->tables();
-  if (kb.flags & SB_OBS_BROADCAST) {
-    const int mode = adj ? 1 : 0;
-    if (ctx->sweep_bpc[mode] == 0) ctx->sweep_bpc[mode] = sbk::sweep_blocks_per_cu(adj, ctx->km, ctx->max_pts);
-    long grid = (long)ctx->n_cu * ctx->sweep_bpc[mode];
-    if (grid > kb.n_sn) grid = kb.n_sn;
-    if (grid < 1) grid = 1;
-    const unsigned slot = ctx->next_counter.fetch_add(1) % SB_N_COUNTERS;
-    kb.counter = ctx->d_counters + slot;
-    e = sbk::launch_sweep(adj, ctx->km, tb, kb, (int)grid, st);
-  } else {
-    e = sbk::launch_sn(adj, ctx->km, tb, kb, st);
-  }
+  e = sbk::launch_sn(adj, ctx->km, ctx->tables(), kb, st);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return SB_OK;
 }

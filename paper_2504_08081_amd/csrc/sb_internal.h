@@ -21,6 +21,7 @@ enum : int { EFLAG_WINDOW = 1, EFLAG_BAND = 2, EFLAG_CSR = 4 };
 struct KModel {
   int n_phase, n_wave, row_pad, n_bands;
   float phase0, inv_dphase, wave0, inv_dwave;
+  double phase0_d, inv_dphase_d, wave0_d, inv_dwave_d;   // grid coordinates are formed in FP64
   float cl_b, cl_inv_span;
   int cl_deg;
   float cl[SB_MAX_CL_DEGREE];    // a_1..a_deg
@@ -45,19 +46,14 @@ struct KBatch {
   const float *data, *w, *cot;
   float *flux, *grad, *jac, *chi2;
   int* err;
-  int* counter;    // work counter of the persistent sweep kernel
 };
 
 // Dynamic LDS bytes of the per-supernova pipeline.
 size_t lds_bytes(const KModel& m, int max_pts, bool adj);
 
-// One workgroup per supernova (forward, or forward + adjoint).
+// One workgroup per supernova, or per parameter sample when the batch shares
+// one observation table (forward, or forward + adjoint).
 hipError_t launch_sn(bool adj, const KModel& m, const KTables& tb, const KBatch& b, hipStream_t st);
-
-// Persistent sweep over parameter samples sharing one observation table.
-hipError_t launch_sweep(bool adj, const KModel& m, const KTables& tb, const KBatch& b, int grid,
-                        hipStream_t st);
-int sweep_blocks_per_cu(bool adj, const KModel& m, int max_pts);
 
 // ------------------------------------------------------------------ fit server
 

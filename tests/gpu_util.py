@@ -67,3 +67,14 @@ def jac_rel_err(j_gpu, j64, x0_per_obs, offsets=None):
     den = np.maximum(np.abs(b), floor)
     den = np.where(den > 0, den, 1.0)
     return np.abs(a - b) / den
+
+
+def grad_norm_err(g_gpu, g64, x0):
+    """Norm-wise error per supernova: max_q |g~ - g~64| / max_q |g~64| on scaled gradients."""
+    sc = PARAM_SCALE[None, :] * np.ones((len(x0), 1))
+    sc[:, 2] = np.asarray(x0, np.float64)
+    a = np.asarray(g_gpu, np.float64) * sc
+    b = np.asarray(g64, np.float64) * sc
+    den = np.abs(b).max(axis=1)
+    den = np.where(den > 0, den, 1.0)
+    return np.abs(a - b).max(axis=1) / den

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import (FLUX_TOL, GRAD_TOL, flux_rel_err, grad_rel_err, jac_rel_err, to_dev,
+from gpu_util import (FLUX_TOL, GRAD_TOL, flux_rel_err, grad_norm_err, grad_rel_err, jac_rel_err, to_dev,
                       torch_or_skip)
 
 pytestmark = pytest.mark.gpu
@@ -164,7 +164,9 @@ def test_cfg3_chi2_gradient_full_size_sampled(ctx6, o6, cfg2, torch):
     eg = grad_rel_err(grad, g64, sub_ev.x0)
     ec = np.abs(chi2 - c64) / np.abs(c64)
     ef = flux_rel_err(r["flux"].cpu().numpy()[sel], f64, sub_ev.sn_offsets)
-    print(f"cfg3: grad rel err max {eg.max():.3e} (per param {eg.max(axis=0)}), chi2 {ec.max():.3e}, flux {ef.max():.3e}")
+    en = grad_norm_err(grad, g64, sub_ev.x0)
+    print(f"cfg3: grad rel err max {eg.max():.3e} (per param {eg.max(axis=0)}), norm-wise {en.max():.3e}, "
+          f"chi2 {ec.max():.3e}, flux {ef.max():.3e}")
     assert eg.max() <= GRAD_TOL
     assert ec.max() <= 1e-4
     assert ef.max() <= FLUX_TOL
