@@ -182,6 +182,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--sweep-samples", type=int, default=1 << 20)
     ap.add_argument("--legs", default="fwd,sweep,big,serve")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one device copy of this size (for calibrating HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -255,6 +257,16 @@ def main():
         "kernel_evals_per_s": n_obs / kern_s,
     }
     log(f"main: {value:.3e} evals/s, kernel {durs.mean():.4f} ms, {achieved:.2f} TFLOP/s algorithmic")
+
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_probe_bytes"] = n * 4
+        del src, dst
 
     if "fwd" in legs:
         d_nochi = {k: D[k] for k in ("z", "t0", "x0", "x1", "c", "t", "band", "sn_offsets")}

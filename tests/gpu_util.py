@@ -78,3 +78,22 @@ def grad_norm_err(g_gpu, g64, x0):
     den = np.abs(b).max(axis=1)
     den = np.where(den > 0, den, 1.0)
     return np.abs(a - b).max(axis=1) / den
+
+
+U32 = 2.0 ** -24
+
+
+def grad_cond_excess(g_gpu, g64, x0, cot, J64, offsets, c=8.0):
+    """Component error of sum_i cot_i J_i over the FP32 conditioning bound c*u*sum_i |cot_i| max_q |J~_iq|
+    (each Jacobian row carries a few ulp of its largest scaled entry); values <= 1 pass."""
+    sc = PARAM_SCALE[None, :] * np.ones((len(x0), 1))
+    sc[:, 2] = np.asarray(x0, np.float64)
+    n_s = np.diff(offsets)
+    sc_obs = np.repeat(sc, n_s, axis=0)
+    row = np.abs(np.asarray(J64, np.float64) * sc_obs).max(axis=1)
+    mag = np.zeros(len(x0))
+    for s in range(len(x0)):
+        lo, hi = int(offsets[s]), int(offsets[s + 1])
+        mag[s] = np.sum(np.abs(np.asarray(cot, np.float64)[lo:hi]) * row[lo:hi])
+    err = np.abs((np.asarray(g_gpu, np.float64) - np.asarray(g64, np.float64)) * sc)
+    return err / np.maximum(c * U32 * mag[:, None], 1e-300)

@@ -8,8 +8,8 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import (FLUX_TOL, GRAD_TOL, flux_rel_err, grad_norm_err, grad_rel_err, jac_rel_err, to_dev,
-                      torch_or_skip)
+from gpu_util import (FLUX_TOL, GRAD_TOL, flux_rel_err, grad_cond_excess, grad_norm_err, grad_rel_err,
+                      jac_rel_err, to_dev, torch_or_skip)
 
 pytestmark = pytest.mark.gpu
 
@@ -96,7 +96,10 @@ def test_cfg1_jacobian_rows(ctx4, o4, torch):
 # ----------------------------------------------------------------------------- small full batch
 
 def test_small_batch_every_result(ctx6, o6, torch):
-    """A 96-supernova batch: every flux, Jacobian row and cotangent gradient against the oracle."""
+    """A 96-supernova batch (1-300 observations each): every flux, Jacobian row and cotangent
+    gradient against the oracle.  With random cotangents a gradient component can cancel by
+    hundreds across observations, so besides the norm-wise 1e-4 bound each component is held to
+    the FP32 conditioning bound of its sum."""
     b = synth.random_batch(31, 96, 1, 300, synth.make_bands(6), synth.make_model())
     g = np.random.default_rng(7)
     cot = g.normal(size=b.n_obs).astype(np.float32)
@@ -106,8 +109,13 @@ def test_small_batch_every_result(ctx6, o6, torch):
     ef = flux_rel_err(f, f64, b.sn_offsets)
     ej = jac_rel_err(J, J64, x0_per_obs(b), b.sn_offsets)
     eg = grad_rel_err(grad, g64, b.x0)
-    print(f"small batch: flux {ef.max():.3e} jac {ej.max():.3e} grad {eg.max():.3e}")
-    assert ef.max() <= FLUX_TOL and ej.max() <= GRAD_TOL and eg.max() <= GRAD_TOL
+    en = grad_norm_err(grad, g64, b.x0)
+    ec = grad_cond_excess(grad, g64, b.x0, cot, J64, b.sn_offsets)
+    print(f"small batch: flux {ef.max():.3e} jac {ej.max():.3e} grad component-wise {eg.max():.3e} "
+          f"norm-wise {en.max():.3e} over conditioning bound {ec.max():.3f}")
+    assert ef.max() <= FLUX_TOL and ej.max() <= GRAD_TOL
+    assert en.max() <= GRAD_TOL
+    assert np.all((eg <= GRAD_TOL) | (ec <= 1.0))
     f_fwd = run_fwd(ctx6, b, torch)
     assert flux_rel_err(f_fwd, f64, b.sn_offsets).max() <= FLUX_TOL
 

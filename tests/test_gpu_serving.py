@@ -122,8 +122,10 @@ def test_budget_and_tick_split_do_not_change_results(sb, model, bands6, requests
 
 
 def test_invalid_requests_rejected(sb, model, bands6, requests):
-    ctx = sb.Context.from_model(model, bands6, hbm_budget_bytes=4096)
     r, d, sig, _ = requests[0]
+    # a budget of 16 bytes per observation leaves no room for the fit's state: the request alone
+    # exceeds it
+    ctx = sb.Context.from_model(model, bands6, hbm_budget_bytes=16 * len(r.t))
 
     def expect(status, **kw):
         a = dict(t=r.t, band=r.band, data=d, sigma=sig, z=r.z, t0=r.theta_init[0], x0=r.theta_init[1],
@@ -145,7 +147,7 @@ def test_invalid_requests_rejected(sb, model, bands6, requests):
     expect(sb.SB_ERR_ARG, t=np.zeros(0, np.float32), band=np.zeros(0, np.int32), data=np.zeros(0, np.float32),
            sigma=np.ones(0, np.float32))
     expect(sb.SB_ERR_ARG, z=0.95, band=np.zeros(n, np.int32))   # band 0 leaves the grid at z = 0.95
-    expect(sb.SB_ERR_BUDGET)                                     # 4 KiB budget < one request
+    expect(sb.SB_ERR_BUDGET)
     ctx.close()
 
 
