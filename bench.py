@@ -31,14 +31,18 @@ METRIC = "bandflux evals/s (fwd, fwd+adjoint) vs FP64 err; p50/p99 fit latency"
 PEAK_FP32_TFLOPS = 157.3       # MI355X vector FP32 (packed); the build disables packed FP32 (half of it)
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic work per unit of the implemented algorithm (flops):
-#   per quadrature point of a (supernova, band): FWD 30, VJP 60
-#   per (point, tap) gather into the weight vectors: 1 add per weight vector (FWD 1, VJP 3)
-#   per (surface row, window column) of the row projections: FWD 2 FMA = 4, VJP 5 FMA = 10
-#   per observation: FWD 24, VJP 90
-W_PT = {"fwd": 30, "vjp": 60}
-W_TAP = {"fwd": 1, "vjp": 3}
-W_CELL = {"fwd": 4, "vjp": 10}
+# Algorithmic work per unit of the implemented algorithm (flops, an FMA counts 2):
+#   per quadrature point of a (supernova, band): grid coordinate 4, colour law 8 (VJP 14),
+#     exp 1, weight factors 1 (VJP 5), fraction 1 ........................ FWD 15, VJP 25
+#   per (point, tap) pair gathered into the weight vectors: tap weight 5, one FMA per
+#     weight vector (VJP: 4, plus the difference weight 4) ................ FWD 7, VJP 17
+#   per (surface row, window column) of the row projections: FWD 2 FMA = 4; VJP two
+#     differences, 2 FMA for the combined node and difference, 5 FMA = 16
+#   per observation: phase coordinate 4, weights 10, taps 8 (VJP 40), partials and
+#     cotangent (VJP 30) .................................................. FWD 24, VJP 90
+W_PT = {"fwd": 15, "vjp": 25}
+W_TAP = {"fwd": 7, "vjp": 17}
+W_CELL = {"fwd": 4, "vjp": 16}
 W_OBS = {"fwd": 24, "vjp": 90}
 
 

@@ -18,8 +18,9 @@ struct SnShared {
   unsigned mask[2];
   int rlo[SB_MAX_BANDS];
   int rhi[SB_MAX_BANDS];
+  int slot_of[SB_MAX_BANDS];   // band -> its slot in the current group, -1 otherwise
+  int slot_ok[BAND_GROUP];
   int flag;
-  int item;
   float red[NWAVES * 8];
 };
 
@@ -41,6 +42,7 @@ __device__ inline void write_obs(const KBatch& b, size_t o, float f, const float
 template <int MODE, bool BCAST>
 __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int sn, const Lds& L,
                         SnShared& S) {
+  constexpr int NR = ModeInfo<MODE>::NR;
   const int tid = threadIdx.x;
   const bool chi2 = (b.flags & SB_OUT_CHI2) != 0;
   const float z = b.z[sn], t0 = b.t0[sn], x0 = b.x0[sn], x1 = b.x1[sn], c = b.c[sn];
@@ -61,7 +63,7 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
   }
   const size_t obase = BCAST ? (size_t)sn * (size_t)b.n_obs : 0;
 
-  reset_scan(S.mask, S.rlo, S.rhi);
+  reset_scan(S.mask, S.rlo, S.rhi, S.slot_of);
   __syncthreads();
 
   // acc: gradient (z, t0, x0, x1, c) and chi2
@@ -100,78 +102,105 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
   }
   __syncthreads();
 
-  const unsigned masks[2] = {(unsigned)uni((int)S.mask[0]), (unsigned)uni((int)S.mask[1])};
-  for (int h = 0; h < 2; ++h) {
-    unsigned msk = masks[h];
-    while (msk) {
-      const int bd = h * 32 + __ffs(msk) - 1;
-      msk &= msk - 1;
-      const int rlo = uni(S.rlo[bd]), rhi = uni(S.rhi[bd]);
-      const bool ok = band_rows<MODE>(m, tb, bd, s64, c, x1, rlo, rhi, L, &S.flag);
-      if (!ok && tid == 0) atomicOr(b.err, EFLAG_WINDOW);
-      constexpr int NR = ModeInfo<MODE>::NR;
-      for (int i = lo + tid; i < hi; i += WG) {
-        if (b.band[i] != bd) continue;
-        const PhaseCell pc = phase_cell(b.t[i], t0, s64, m);
-        if (!pc.in) continue;
-        float f, dv[5];
-        if (!ok) {
-          f = qnan;
-#pragma unroll
-          for (int q = 0; q < 5; ++q) dv[q] = qnan;
-        } else {
-          float wp[4];
-          cr_weights(pc.x, pc.edge, wp);
-          const int tb0 = pc.edge ? 1 : 0, tb1 = pc.edge ? 3 : 4;
-          float Sx = 0.f;
-          if (MODE == FWD) {
-            for (int t = tb0; t < tb1; ++t) Sx = fmaf(wp[t], L.R[row_index(pc.a - 1 + t, rlo, rhi) * NR], Sx);
-            f = A * Sx;
-          } else {
-            float dw[4];
-            cr_dweights(pc.x, pc.edge, dw);
-            float S1 = 0.f, Sc = 0.f, Sl = 0.f, Sp = 0.f;
-            for (int t = tb0; t < tb1; ++t) {
-              const float* r = L.R + row_index(pc.a - 1 + t, rlo, rhi) * NR;
-              Sx = fmaf(wp[t], r[0], Sx);
-              Sp = fmaf(dw[t], r[0], Sp);
-              S1 = fmaf(wp[t], r[1], S1);
-              Sc = fmaf(wp[t], r[2], Sc);
-              if (MODE == VJP) Sl = fmaf(wp[t], r[3], Sl);
-            }
-            Sp *= m.inv_dphase;
-            f = A * Sx;
-            const float As = A * s;
-            dv[0] = -s * f - As * fmaf(pc.p, Sp, Sl);   // z
-            dv[1] = -As * Sp;                           // t0
-            dv[2] = s * Sx;                             // x0
-            dv[3] = A * S1;                             // x1
-            dv[4] = A * Sc;                             // c
-          }
+  unsigned rem0 = (unsigned)uni((int)S.mask[0]), rem1 = (unsigned)uni((int)S.mask[1]);
+  while (rem0 | rem1) {
+    unsigned g0, g1;
+    take_group(rem0, rem1, g0, g1);
+    // row projections of every band of the group
+    int sl = 0;
+    for (int h = 0; h < 2; ++h) {
+      unsigned gm = h ? g1 : g0;
+      while (gm) {
+        const int bd = h * 32 + __ffs(gm) - 1;
+        gm &= gm - 1;
+        const bool ok = band_rows<MODE>(m, tb, bd, s64, c, x1, uni(S.rlo[bd]), uni(S.rhi[bd]), L,
+                                        L.R + (size_t)sl * m.n_phase * NR, &S.flag);
+        if (tid == 0) {
+          S.slot_of[bd] = sl;
+          S.slot_ok[sl] = ok ? 1 : 0;
+          if (!ok) atomicOr(b.err, EFLAG_WINDOW);
         }
-        if (MODE == FWD) {
-          if (chi2) {
-            const float r = f - b.data[i];
-            acc[5] = fmaf(r * r, b.w[i], acc[5]);
-          } else {
-            b.flux[obase + i] = f;
-          }
-        } else {
-          write_obs<MODE>(b, obase + i, f, dv);
-          float gbar;
-          if (chi2) {
-            const float r = f - b.data[i];
-            const float wi = b.w[i];
-            acc[5] = fmaf(r * r, wi, acc[5]);
-            gbar = 2.f * r * wi;
-          } else {
-            gbar = b.cot[obase + i];
-          }
+        ++sl;
+      }
+    }
+    __syncthreads();
+
+    // every observation of the group's bands, in one pass
+    for (int i = lo + tid; i < hi; i += WG) {
+      const int bd = b.band[i];
+      if ((unsigned)bd >= (unsigned)m.n_bands) continue;
+      const int slot = S.slot_of[bd];
+      if (slot < 0) continue;
+      const PhaseCell pc = phase_cell(b.t[i], t0, s64, m);
+      if (!pc.in) continue;
+      const int rlo = S.rlo[bd], rhi = S.rhi[bd];
+      const float* Rb = L.R + (size_t)slot * m.n_phase * NR;
+      float f, dv[5];
+      if (!S.slot_ok[slot]) {
+        f = qnan;
 #pragma unroll
-          for (int q = 0; q < 5; ++q) acc[q] = fmaf(gbar, dv[q], acc[q]);
+        for (int q = 0; q < 5; ++q) dv[q] = qnan;
+      } else {
+        float wp[4];
+        cr_weights(pc.x, pc.edge, wp);
+        const int tb0 = pc.edge ? 1 : 0, tb1 = pc.edge ? 3 : 4;
+        float Sx = 0.f;
+        if (MODE == FWD) {
+          for (int t = tb0; t < tb1; ++t) Sx = fmaf(wp[t], Rb[row_clamp(pc.a - 1 + t, rlo, rhi) * NR], Sx);
+          f = A * Sx;
+        } else {
+          float dw[4];
+          cr_dweights(pc.x, pc.edge, dw);
+          float S1 = 0.f, Sc = 0.f, Sl = 0.f, Sp = 0.f;
+          for (int t = tb0; t < tb1; ++t) {
+            const float* r = Rb + row_clamp(pc.a - 1 + t, rlo, rhi) * NR;
+            Sx = fmaf(wp[t], r[0], Sx);
+            Sp = fmaf(dw[t], r[0], Sp);
+            S1 = fmaf(wp[t], r[1], S1);
+            Sc = fmaf(wp[t], r[2], Sc);
+            if (MODE == VJP) Sl = fmaf(wp[t], r[3], Sl);
+          }
+          Sp *= m.inv_dphase;
+          f = A * Sx;
+          const float As = A * s;
+          dv[0] = -s * f - As * fmaf(pc.p, Sp, Sl);   // z
+          dv[1] = -As * Sp;                           // t0
+          dv[2] = s * Sx;                             // x0
+          dv[3] = A * S1;                             // x1
+          dv[4] = A * Sc;                             // c
         }
       }
-      __syncthreads();
+      if (MODE == FWD) {
+        if (chi2) {
+          const float r = f - b.data[i];
+          acc[5] = fmaf(r * r, b.w[i], acc[5]);
+        } else {
+          b.flux[obase + i] = f;
+        }
+      } else {
+        write_obs<MODE>(b, obase + i, f, dv);
+        float gbar;
+        if (chi2) {
+          const float r = f - b.data[i];
+          const float wi = b.w[i];
+          acc[5] = fmaf(r * r, wi, acc[5]);
+          gbar = 2.f * r * wi;
+        } else {
+          gbar = b.cot[obase + i];
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc[q] = fmaf(gbar, dv[q], acc[q]);
+      }
+    }
+    __syncthreads();
+    // release the group's slots
+    for (int h = 0; h < 2; ++h) {
+      unsigned gm = h ? g1 : g0;
+      while (gm) {
+        const int bd = h * 32 + __ffs(gm) - 1;
+        gm &= gm - 1;
+        if (tid == 0) S.slot_of[bd] = -1;
+      }
     }
   }
 
@@ -193,13 +222,13 @@ template <int MODE, bool BCAST>
 __global__ __launch_bounds__(WG) void k_sn(KModel m, KTables tb, KBatch b) {
   extern __shared__ __align__(16) char smem[];
   __shared__ SnShared S;
-  const Lds L = lds_carve<MODE>(smem, m, tb.max_pts);
+  const Lds L = lds_carve<MODE>(smem, m, tb);
   sn_body<MODE, BCAST>(m, tb, b, blockIdx.x, L, S);
 }
 
-size_t lds_bytes(const KModel& m, int max_pts, bool adj) {
-  return adj ? lds_layout_bytes<VJP>(m.n_phase, m.n_wave, max_pts)
-             : lds_layout_bytes<FWD>(m.n_phase, m.n_wave, max_pts);
+size_t lds_bytes(const KModel& m, int max_pts, int jcap, bool adj) {
+  return adj ? lds_layout_bytes<VJP>(m.n_phase, max_pts, jcap)
+             : lds_layout_bytes<FWD>(m.n_phase, max_pts, jcap);
 }
 
 template <typename K>
@@ -210,7 +239,7 @@ static hipError_t prep_lds(K kern, size_t bytes) {
 
 template <int MODE, bool BCAST>
 static hipError_t launch_one(const KModel& m, const KTables& tb, const KBatch& b, hipStream_t st) {
-  const size_t lds = lds_layout_bytes<MODE>(m.n_phase, m.n_wave, tb.max_pts);
+  const size_t lds = lds_layout_bytes<MODE>(m.n_phase, tb.max_pts, tb.jcap);
   hipError_t e = prep_lds(k_sn<MODE, BCAST>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_sn<MODE, BCAST>), dim3(b.n_sn), dim3(WG), lds, st, m, tb, b);

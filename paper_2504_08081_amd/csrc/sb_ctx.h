@@ -32,6 +32,7 @@ struct sb_ctx {
   int* d_err = nullptr;
   int n_bands = 0;
   int max_pts = 0;
+  int jcap = 0;
   std::vector<double> band_lo, band_hi; // sample range of each band
   int n_cu = 1;
   size_t max_lds = 65536;
@@ -44,6 +45,7 @@ struct sb_ctx {
     t.pts = d_pts;
     t.npts = d_npts;
     t.max_pts = max_pts;
+    t.jcap = jcap;
     return t;
   }
 };

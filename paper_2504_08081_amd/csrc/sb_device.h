@@ -41,14 +41,19 @@ __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 //   VJP: Rx, R1, Rc, Rl           (all five partials, including z)
 enum Mode { FWD = 0, FIT = 1, VJP = 2 };
 
-// NP per-point arrays, NG weight vectors, NR row projections.
-//   FWD: P                                   | G               | Rx
-//   FIT: P, Pc                               | G, Gc           | Rx, R1, Rc
-//   VJP: P, Pc, Plc (4 taps), Pd (3 taps)    | G, Gc, Glc, Gd  | Rx, R1, Rc, Rl
+// Per mode: NG weight vectors, interleaved per point tap and per window column
+// as one vector type (float / float2 / float4), and NR row projections.
+//   FWD: G                  | Rx
+//   FIT: G, Gc              | Rx, R1, Rc
+//   VJP: G, Gc, Glc, Gd     | Rx, R1, Rc, Rl
 template <int MODE> struct ModeInfo;
-template <> struct ModeInfo<FWD> { static constexpr int NP = 4, NG = 1, NR = 1; };
-template <> struct ModeInfo<FIT> { static constexpr int NP = 8, NG = 2, NR = 3; };
-template <> struct ModeInfo<VJP> { static constexpr int NP = 15, NG = 4, NR = 4; };
+template <> struct ModeInfo<FWD> { static constexpr int NG = 1, NR = 1; typedef float V; };
+template <> struct ModeInfo<FIT> { static constexpr int NG = 2, NR = 3; typedef float2 V; };
+template <> struct ModeInfo<VJP> { static constexpr int NG = 4, NR = 4; typedef float4 V; };
+
+// Bands whose row projections are held at once; the observations of a group
+// are finished in one pass.
+constexpr int BAND_GROUP = 8;
 
 // Catmull-Rom (Keys a = -1/2) weights of the four nodes a-1..a+2 at fraction x of
 // cell a; linear weights (nodes a, a+1 only) in the first and last cell.
@@ -135,75 +140,127 @@ __device__ inline void colour_law(float mu, const KModel& m, float& cl, float& d
   dcl = d * m.cl_inv_span;
 }
 
-// Pointers into the dynamic LDS of one workgroup.
+// Pointers into the dynamic LDS of one workgroup (one wave, one supernova).
 struct Lds {
-  float* P;    // [NP][max_pts]      point weights per tap
-  int* j0;     // [max_pts]          wavelength cell per point
-  int* kf;     // [n_wave + 2]       first point of each cell
-  float* G;    // [NG][n_wave + 4]   weight vectors over the window
-  float* RP;   // [NWAVES][64][NR]   per-wave partial row projections
-  float* R;    // [n_phase][NR]      row projections of the current band
-  int gstride; // n_wave + 4
+  void* P;     // [max_pts] of V             weight factors per quadrature point
+  float* x;    // [max_pts]                  fraction in the point's wavelength cell
+  int* j0;     // [max_pts]                  wavelength cell per point
+  int* kf;     // [jcap + 2]                 first point of each cell
+  void* G;     // [jcap] of V                weight vectors over the window
+  float* R;    // [BAND_GROUP][n_phase][NR]  row projections of the bands of a group
 };
 
 template <int MODE>
-__host__ __device__ inline size_t lds_layout_bytes(int n_phase, int n_wave, int max_pts) {
-  constexpr int NP = ModeInfo<MODE>::NP, NG = ModeInfo<MODE>::NG, NR = ModeInfo<MODE>::NR;
+__host__ __device__ inline size_t lds_layout_bytes(int n_phase, int max_pts, int jcap) {
+  typedef typename ModeInfo<MODE>::V V;
+  constexpr int NR = ModeInfo<MODE>::NR;
   size_t b = 0;
-  b += (size_t)NP * max_pts * sizeof(float);
+  b += (size_t)max_pts * sizeof(V);
+  b += (size_t)max_pts * sizeof(float);
   b += (size_t)max_pts * sizeof(int);
-  b += (size_t)(n_wave + 2) * sizeof(int);
-  b += (size_t)NG * (n_wave + 4) * sizeof(float);
-  b += (size_t)NWAVES * 64 * NR * sizeof(float);
-  b += (size_t)n_phase * NR * sizeof(float);
+  b += (size_t)(jcap + 2) * sizeof(int);
+  b = (b + 15) & ~(size_t)15;
+  b += (size_t)jcap * sizeof(V);
+  b += (size_t)BAND_GROUP * n_phase * NR * sizeof(float);
   return b;
 }
 
 template <int MODE>
-__device__ inline Lds lds_carve(char* base, const KModel& m, int max_pts) {
-  constexpr int NP = ModeInfo<MODE>::NP, NG = ModeInfo<MODE>::NG, NR = ModeInfo<MODE>::NR;
+__device__ inline Lds lds_carve(char* base, const KModel& m, const KTables& tb) {
+  typedef typename ModeInfo<MODE>::V V;
   Lds L;
-  char* p = base;
-  L.P = (float*)p;  p += (size_t)NP * max_pts * sizeof(float);
-  L.j0 = (int*)p;   p += (size_t)max_pts * sizeof(int);
-  L.kf = (int*)p;   p += (size_t)(m.n_wave + 2) * sizeof(int);
-  L.G = (float*)p;  p += (size_t)NG * (m.n_wave + 4) * sizeof(float);
-  L.RP = (float*)p; p += (size_t)NWAVES * 64 * NR * sizeof(float);
-  L.R = (float*)p;
-  L.gstride = m.n_wave + 4;
+  size_t o = 0;
+  L.P = base + o;            o += (size_t)tb.max_pts * sizeof(V);
+  L.x = (float*)(base + o);  o += (size_t)tb.max_pts * sizeof(float);
+  L.j0 = (int*)(base + o);   o += (size_t)tb.max_pts * sizeof(int);
+  L.kf = (int*)(base + o);   o += (size_t)(tb.jcap + 2) * sizeof(int);
+  o = (o + 15) & ~(size_t)15;
+  L.G = base + o;            o += (size_t)tb.jcap * sizeof(V);
+  L.R = (float*)(base + o);
   return L;
 }
 
-// Row projections of one (supernova, band) for rows [rlo, rhi]:
-//   R[(a - rlo)*NR + 0] = sum_j G(j)  (M0 + x1 M1)[a, j]
-//   R[...+1]            = sum_j G(j)  M1[a, j]                          (FIT, VJP)
-//   R[...+2]            = sum_j Gc(j) (M0 + x1 M1)[a, j]                (FIT, VJP)
-//   R[...+3]            = sum_j Glc(j) (M0 + x1 M1)[a, j]
-//                       + sum_j Gd(j) (D0 + x1 D1)[a, j]                (VJP)
+template <typename V> __device__ inline V vzero();
+template <> __device__ inline float vzero<float>() { return 0.f; }
+template <> __device__ inline float2 vzero<float2>() { return make_float2(0.f, 0.f); }
+template <> __device__ inline float4 vzero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+
+// Catmull-Rom weight of tap t (node a-1+t of cell a) at fraction x; linear in edge cells.
+template <int T>
+__device__ inline float cr_tap(float x, bool edge) {
+  if (edge) return T == 1 ? 1.f - x : (T == 2 ? x : 0.f);
+  if (T == 0) return ((-0.5f * x + 1.f) * x - 0.5f) * x;
+  if (T == 1) return (1.5f * x - 2.5f) * x * x + 1.f;
+  if (T == 2) return ((-1.5f * x + 2.f) * x + 0.5f) * x;
+  return (0.5f * x - 0.5f) * x * x;
+}
+
+// Difference weight e_t of tap t (difference D(a-1+t)); edge cells use D(a) only.
+template <int T>
+__device__ inline float cr_diff_tap(float x, bool edge) {
+  if (edge) return T == 1 ? 1.f : 0.f;
+  if (T == 0) return (1.5f * x - 2.f) * x + 0.5f;
+  if (T == 1) return (-3.f * x + 3.f) * x + 0.5f;
+  if (T == 2) return (1.5f * x - 1.f) * x;
+  return 0.f;
+}
+
+// Adds the tap-T contributions of the points of cell q to the weight vector g.
+template <int MODE, int T>
+__device__ inline void gather_cell(typename ModeInfo<MODE>::V& g, const Lds& L, int k0, int k1, bool edge) {
+  typedef typename ModeInfo<MODE>::V V;
+  const V* Pv = (const V*)L.P;
+  for (int k = k0; k < k1; ++k) {
+    const float x = L.x[k];
+    const float w = cr_tap<T>(x, edge);
+    const V p = Pv[k];
+    if constexpr (MODE == FWD) {
+      g = fmaf(p, w, g);
+    } else if constexpr (MODE == FIT) {
+      g.x = fmaf(p.x, w, g.x);
+      g.y = fmaf(p.y, w, g.y);
+    } else {
+      g.x = fmaf(p.x, w, g.x);
+      g.y = fmaf(p.y, w, g.y);
+      g.z = fmaf(p.z, w, g.z);
+      if (T < 3) g.w = fmaf(p.w, cr_diff_tap<T>(x, edge), g.w);
+    }
+  }
+}
+
+// Row projections of one (supernova, band) for rows [rlo, rhi], written to
+// Rb[a*NR + r] for the absolute row a:
+//   r=0  sum_j G(j)  (M0 + x1 M1)[a, j]
+//   r=1  sum_j G(j)  M1[a, j]                          (FIT, VJP)
+//   r=2  sum_j Gc(j) (M0 + x1 M1)[a, j]                (FIT, VJP)
+//   r=3  sum_j Glc(j) (M0 + x1 M1)[a, j]
+//        + sum_j Gd(j) (D0 + x1 D1)[a, j]              (VJP)
 // with om_k = W_k exp(c CL(mu_k)) and
 //   G(j)   = sum_k om_k wl_j(mu_k),          Gc(j) = sum_k om_k CL(mu_k) wl_j(mu_k),
 //   Glc(j) = sum_k om_k mu_k c CL'(mu_k) wl_j(mu_k),
 //   Gd(j)  = sum_k om_k mu_k e_j(mu_k) / dwave   (difference weights, D(j) = M(j+1) - M(j)),
-// so that Rl gives sum_k om_k mu_k [dI/dmu + c CL' I] at the phase rows.
-// All threads of the workgroup must call it (it holds barriers).  Returns
-// false, uniformly, when the band's rest window leaves the wavelength grid.
-// *flag is an LDS int used as scratch.
+// so that r=3 gives sum_k om_k mu_k [dI/dmu + c CL' I] at the phase rows.
+// All threads of the workgroup must call it.  Returns false, uniformly, when
+// the band's rest window leaves the wavelength grid (or exceeds the window
+// capacity, which covers z > -1/2).  *flag is an LDS int used as scratch.
 template <int MODE>
 __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, float c, float x1,
-                          int rlo, int rhi, const Lds& L, int* flag) {
-  constexpr int NG = ModeInfo<MODE>::NG, NR = ModeInfo<MODE>::NR;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+                          int rlo, int rhi, const Lds& L, float* Rb, int* flag) {
+  typedef typename ModeInfo<MODE>::V V;
+  constexpr int NR = ModeInfo<MODE>::NR;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int np = uni(tb.npts[bd]);
   bd = uni(bd);
   rlo = uni(rlo);
   rhi = uni(rhi);
   const float2* pts = tb.pts + (size_t)bd * SB_MAX_BAND_POINTS;
-  const int P = tb.max_pts;
+  V* Pv = (V*)L.P;
+  V* Gv = (V*)L.G;
 
   if (tid == 0) *flag = 0;
   __syncthreads();
 
-  // (1) quadrature points: wavelength cell, tap weights times om_k
+  // (1) quadrature points: wavelength cell and fraction, weight factors om_k...
   for (int k = tid; k < np; k += WG) {
     const float2 lw = pts[k];
     float x, mu;
@@ -221,30 +278,18 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
       mu = (float)mu_d;
     }
     if (!ok) *flag = 1;
-    const bool edge = (j0 == 0) || (j0 == m.n_wave - 2);
     float cl, dcl;
     colour_law(mu, m, cl, dcl);
     const float om = lw.y * expf(c * cl);
-    float w[4];
-    cr_weights(x, edge, w);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) L.P[t * P + k] = om * w[t];
-    if (MODE != FWD) {
-      const float omc = om * cl;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) L.P[(4 + t) * P + k] = omc * w[t];
-    }
-    if (MODE == VJP) {
-      float e[3];
-      cr_diff_weights(x, edge, e);
+    if constexpr (MODE == FWD) {
+      Pv[k] = om;
+    } else if constexpr (MODE == FIT) {
+      Pv[k] = make_float2(om, om * cl);
+    } else {
       const float omu = om * mu;
-      const float omlc = omu * (c * dcl);
-      const float omd = omu * m.inv_dwave;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) L.P[(8 + t) * P + k] = omlc * w[t];
-#pragma unroll
-      for (int t = 0; t < 3; ++t) L.P[(12 + t) * P + k] = omd * e[t];
+      Pv[k] = make_float4(om, om * cl, omu * (c * dcl), omu * m.inv_dwave);
     }
+    L.x[k] = x;
     L.j0[k] = j0;
   }
   __syncthreads();
@@ -253,6 +298,10 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   // (2) first point of every wavelength cell touched (cells are non-decreasing in k)
   const int j0f = uni(L.j0[0]), j0l = uni(L.j0[np - 1]);
   const int ncell = j0l - j0f + 1;
+  const int j_lo = j0f - 1 < 0 ? 0 : j0f - 1;
+  const int j_hi = j0l + 2 > m.n_wave - 1 ? m.n_wave - 1 : j0l + 2;
+  const int J = j_hi - j_lo + 1;
+  if (J > tb.jcap) return false;
   for (int k = tid; k < np; k += WG) {
     // the clamps only keep every index in bounds
     const int cur = min(max(L.j0[k] - j0f, 0), ncell - 1);
@@ -264,108 +313,136 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
 
   // (3) weight vectors over the window of columns [j_lo, j_hi]; node tap t and
   //     difference tap t of a point in cell j0 both land on column j0 - 1 + t
-  const int j_lo = j0f - 1 < 0 ? 0 : j0f - 1;
-  const int j_hi = j0l + 2 > m.n_wave - 1 ? m.n_wave - 1 : j0l + 2;
-  const int J = j_hi - j_lo + 1;
   for (int col = tid; col < J; col += WG) {
     const int j = j_lo + col;
-    float g[NG];
-#pragma unroll
-    for (int q = 0; q < NG; ++q) g[q] = 0.f;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int q = j - t + 1 - j0f;   // cell whose tap t lands on column j
-      if (q < 0 || q >= ncell) continue;
-      const int k1 = min(L.kf[q + 1], np);
-      for (int k = max(L.kf[q], 0); k < k1; ++k) {
-        g[0] += L.P[t * P + k];
-        if (MODE != FWD) g[1] += L.P[(4 + t) * P + k];
-        if (MODE == VJP) {
-          g[2] += L.P[(8 + t) * P + k];
-          if (t < 3) g[3] += L.P[(12 + t) * P + k];
-        }
-      }
+    V g = vzero<V>();
+#define SB_GATHER_TAP(T)                                                            \
+    {                                                                               \
+      const int cell = j - (T) + 1;                                                 \
+      const int q = cell - j0f;                                                     \
+      if (q >= 0 && q < ncell) {                                                    \
+        const bool edge = (cell == 0) || (cell == m.n_wave - 2);                    \
+        gather_cell<MODE, T>(g, L, max(L.kf[q], 0), min(L.kf[q + 1], np), edge);    \
+      }                                                                             \
     }
-#pragma unroll
-    for (int h = 0; h < NG; ++h) L.G[h * L.gstride + col] = g[h];
+    SB_GATHER_TAP(0)
+    SB_GATHER_TAP(1)
+    SB_GATHER_TAP(2)
+    SB_GATHER_TAP(3)
+#undef SB_GATHER_TAP
+    Gv[col] = g;
   }
   __syncthreads();
 
-  // (4) row projections: lanes over rows, waves over quarters of the window
+  // (4) row projections: lanes over rows, the wave over every window column,
+  //     accumulated in four interleaved chains (columns cc mod 4) that are added
+  //     pairwise at the end.  The column base is uniform (scalar) and the lane's
+  //     row offset is fixed, so a load needs one address add.
   const int nrow = rhi - rlo + 1;
-  const int qc = (J + NWAVES - 1) / NWAVES;
-  const int c0 = min(wv * qc, J), c1 = min(c0 + qc, J);
+  const int last = m.n_wave - 1;
   for (int rb = 0; rb < nrow; rb += 64) {
     const int a = rlo + rb + lane;
     const int a_ld = a < m.n_phase - 1 ? a : m.n_phase - 1;
-    const float2* colp = tb.surf + a_ld;
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
-    if (MODE == VJP) {
-      // carries the next column for the first differences (clamped at the grid end,
-      // where its difference weight is zero)
-      float2 cur = colp[(size_t)min(j_lo + c0, m.n_wave - 1) * m.row_pad];
-#pragma unroll 4
-      for (int cc = c0; cc < c1; ++cc) {
-        const float2 nxt = colp[(size_t)min(j_lo + cc + 1, m.n_wave - 1) * m.row_pad];
+    const float2* col0 = tb.surf + a_ld;
+    float acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[u][r] = 0.f;
+    if constexpr (MODE == VJP) {
+      // first differences need the next column (clamped at the grid end, where the
+      // difference weight is zero)
+      float2 cur = col0[(size_t)j_lo * m.row_pad];
+      int cc = 0;
+      for (; cc + 4 <= J; cc += 4) {
+        float2 mm[5];
+        mm[0] = cur;
+#pragma unroll
+        for (int u = 1; u <= 4; ++u) mm[u] = col0[(size_t)min(j_lo + cc + u, last) * m.row_pad];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float4 g = Gv[cc + u];
+          const float mx = fmaf(x1, mm[u].y, mm[u].x);
+          const float dx = fmaf(x1, mm[u + 1].y - mm[u].y, mm[u + 1].x - mm[u].x);
+          acc[u][0] = fmaf(g.x, mx, acc[u][0]);
+          acc[u][1] = fmaf(g.x, mm[u].y, acc[u][1]);
+          acc[u][2] = fmaf(g.y, mx, acc[u][2]);
+          acc[u][3] = fmaf(g.z, mx, acc[u][3]);
+          acc[u][3] = fmaf(g.w, dx, acc[u][3]);
+        }
+        cur = mm[4];
+      }
+      for (; cc < J; ++cc) {
+        const float2 nxt = col0[(size_t)min(j_lo + cc + 1, last) * m.row_pad];
+        const float4 g = Gv[cc];
         const float mx = fmaf(x1, cur.y, cur.x);
         const float dx = fmaf(x1, nxt.y - cur.y, nxt.x - cur.x);
-        const float g = L.G[cc];
-        acc[0] = fmaf(g, mx, acc[0]);
-        acc[1] = fmaf(g, cur.y, acc[1]);
-        acc[2] = fmaf(L.G[L.gstride + cc], mx, acc[2]);
-        acc[3] = fmaf(L.G[2 * L.gstride + cc], mx, acc[3]);
-        acc[3] = fmaf(L.G[3 * L.gstride + cc], dx, acc[3]);
+        acc[0][0] = fmaf(g.x, mx, acc[0][0]);
+        acc[0][1] = fmaf(g.x, cur.y, acc[0][1]);
+        acc[0][2] = fmaf(g.y, mx, acc[0][2]);
+        acc[0][3] = fmaf(g.z, mx, acc[0][3]);
+        acc[0][3] = fmaf(g.w, dx, acc[0][3]);
         cur = nxt;
       }
     } else {
-      const float2* cp = colp + (size_t)(j_lo + c0) * m.row_pad;
-      int cc = c0;
-      for (; cc + 4 <= c1; cc += 4) {
+      int cc = 0;
+      for (; cc + 4 <= J; cc += 4) {
         float2 mm[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) mm[u] = cp[(size_t)(cc - c0 + u) * m.row_pad];
+        for (int u = 0; u < 4; ++u) mm[u] = col0[(size_t)(j_lo + cc + u) * m.row_pad];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const float g = L.G[cc + u];
+          const V g = Gv[cc + u];
           const float mx = fmaf(x1, mm[u].y, mm[u].x);
-          acc[0] = fmaf(g, mx, acc[0]);
-          if (MODE == FIT) {
-            acc[1] = fmaf(g, mm[u].y, acc[1]);
-            acc[2] = fmaf(L.G[L.gstride + cc + u], mx, acc[2]);
+          if constexpr (MODE == FWD) {
+            acc[u][0] = fmaf(g, mx, acc[u][0]);
+          } else {
+            acc[u][0] = fmaf(g.x, mx, acc[u][0]);
+            acc[u][1] = fmaf(g.x, mm[u].y, acc[u][1]);
+            acc[u][2] = fmaf(g.y, mx, acc[u][2]);
           }
         }
       }
-      for (; cc < c1; ++cc) {
-        const float2 mm = cp[(size_t)(cc - c0) * m.row_pad];
-        const float g = L.G[cc];
+      for (; cc < J; ++cc) {
+        const float2 mm = col0[(size_t)(j_lo + cc) * m.row_pad];
+        const V g = Gv[cc];
         const float mx = fmaf(x1, mm.y, mm.x);
-        acc[0] = fmaf(g, mx, acc[0]);
-        if (MODE == FIT) {
-          acc[1] = fmaf(g, mm.y, acc[1]);
-          acc[2] = fmaf(L.G[L.gstride + cc], mx, acc[2]);
+        if constexpr (MODE == FWD) {
+          acc[0][0] = fmaf(g, mx, acc[0][0]);
+        } else {
+          acc[0][0] = fmaf(g.x, mx, acc[0][0]);
+          acc[0][1] = fmaf(g.x, mm.y, acc[0][1]);
+          acc[0][2] = fmaf(g.y, mx, acc[0][2]);
         }
       }
     }
+    if (rb + lane < nrow) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) L.RP[(wv * 64 + lane) * NR + r] = acc[r];
-    __syncthreads();
-    if (tid < 64 * NR) {
-      const int row = tid / NR, r = tid - row * NR;
-      if (rb + row < nrow) {
-        float v = L.RP[(0 * 64 + row) * NR + r];
-#pragma unroll
-        for (int w2 = 1; w2 < NWAVES; ++w2) v += L.RP[(w2 * 64 + row) * NR + r];
-        L.R[(rb + row) * NR + r] = v;
-      }
+      for (int r = 0; r < NR; ++r) Rb[a * NR + r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
     }
-    __syncthreads();
   }
+  __syncthreads();
   return true;
 }
 
-// Index of surface row a in the row projections of [rlo, rhi] (clamped into range).
-__device__ inline int row_index(int a, int rlo, int rhi) {
-  return min(max(a, rlo), rhi) - rlo;
+// Row a clamped into [rlo, rhi] (the rows whose projections were computed).
+__device__ inline int row_clamp(int a, int rlo, int rhi) { return min(max(a, rlo), rhi); }
+
+// Next group of up to BAND_GROUP bands, lowest ids first, taken out of the
+// remaining band mask (all values uniform).
+__device__ inline void take_group(unsigned& rem0, unsigned& rem1, unsigned& g0, unsigned& g1) {
+  g0 = g1 = 0u;
+  for (int n = 0; n < BAND_GROUP && (rem0 | rem1); ++n) {
+    if (rem0) {
+      const unsigned bit = rem0 & (0u - rem0);
+      g0 |= bit;
+      rem0 &= ~bit;
+    } else {
+      const unsigned bit = rem1 & (0u - rem1);
+      g1 |= bit;
+      rem1 &= ~bit;
+    }
+  }
 }
 
 // Sum of N values over the workgroup in a fixed order; every thread gets the
@@ -397,10 +474,11 @@ __device__ inline void block_sum(float (&v)[N], float* red) {
 
 // Branch-free reset of the per-band scan state (every thread stores the same
 // values), so no lane-dependent branch sits in loops that hold barriers.
-__device__ inline void reset_scan(unsigned* mask, int* rlo, int* rhi) {
+__device__ inline void reset_scan(unsigned* mask, int* rlo, int* rhi, int* slot_of) {
   const int tid = threadIdx.x;
   rlo[tid & (SB_MAX_BANDS - 1)] = 0x7fffffff;
   rhi[tid & (SB_MAX_BANDS - 1)] = -1;
+  slot_of[tid & (SB_MAX_BANDS - 1)] = -1;
   mask[tid & 1] = 0u;
 }
 

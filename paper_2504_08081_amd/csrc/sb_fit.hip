@@ -21,6 +21,8 @@ struct FitShared {
   unsigned mask[2];
   int rlo[SB_MAX_BANDS];
   int rhi[SB_MAX_BANDS];
+  int slot_of[SB_MAX_BANDS];
+  int slot_ok[BAND_GROUP];
   int flag;
   float red[NWAVES * 16];
 };
@@ -40,7 +42,7 @@ __device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, cons
   const float t0 = q[0], x0 = expf(q[1]), x1 = q[2], c = q[3];
   const float s = (float)s64;
   const float A = (float)((double)x0 * s64);
-  reset_scan(S.mask, S.rlo, S.rhi);
+  reset_scan(S.mask, S.rlo, S.rhi, S.slot_of);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 15; ++k) out[k] = 0.f;
@@ -57,59 +59,83 @@ __device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, cons
     atomicOr(&S.mask[bd >> 5], 1u << (bd & 31));
   }
   __syncthreads();
-  const unsigned masks[2] = {(unsigned)uni((int)S.mask[0]), (unsigned)uni((int)S.mask[1])};
   constexpr int NR = ModeInfo<FIT>::NR;
-  for (int h = 0; h < 2; ++h) {
-    unsigned msk = masks[h];
-    while (msk) {
-      const int bd = h * 32 + __ffs(msk) - 1;
-      msk &= msk - 1;
-      const int rlo = uni(S.rlo[bd]), rhi = uni(S.rhi[bd]);
-      const bool ok = band_rows<FIT>(m, tb, bd, s64, c, x1, rlo, rhi, L, &S.flag);
-      if (!ok && tid == 0) atomicOr(F.err, EFLAG_WINDOW);
-      for (int i = tid; i < O.n; i += WG) {
-        if (O.band[i] != bd) continue;
-        const PhaseCell pc = phase_cell(O.t[i], t0, s64, m);
-        if (!pc.in || pc.nan) continue;
-        float J[4], f;
-        if (!ok) {
-          f = __builtin_nanf("");
-          J[0] = J[1] = J[2] = J[3] = f;
-        } else {
-          float wp[4], dw[4];
-          cr_weights(pc.x, pc.edge, wp);
-          cr_dweights(pc.x, pc.edge, dw);
-          const int tb0 = pc.edge ? 1 : 0, tb1 = pc.edge ? 3 : 4;
-          float Sx = 0.f, Sp = 0.f, S1 = 0.f, Sc = 0.f;
-          for (int t = tb0; t < tb1; ++t) {
-            const float* r = L.R + row_index(pc.a - 1 + t, rlo, rhi) * NR;
-            Sx = fmaf(wp[t], r[0], Sx);
-            Sp = fmaf(dw[t], r[0], Sp);
-            S1 = fmaf(wp[t], r[1], S1);
-            Sc = fmaf(wp[t], r[2], Sc);
-          }
-          f = A * Sx;
-          J[0] = -A * s * Sp * m.inv_dphase;   // d/dt0
-          J[1] = f;                            // d/d ln x0
-          J[2] = A * S1;                       // d/dx1
-          J[3] = A * Sc;                       // d/dc
+  unsigned rem0 = (unsigned)uni((int)S.mask[0]), rem1 = (unsigned)uni((int)S.mask[1]);
+  while (rem0 | rem1) {
+    unsigned g0, g1;
+    take_group(rem0, rem1, g0, g1);
+    int sl = 0;
+    for (int h = 0; h < 2; ++h) {
+      unsigned gm = h ? g1 : g0;
+      while (gm) {
+        const int bd = h * 32 + __ffs(gm) - 1;
+        gm &= gm - 1;
+        const bool ok = band_rows<FIT>(m, tb, bd, s64, c, x1, uni(S.rlo[bd]), uni(S.rhi[bd]), L,
+                                       L.R + (size_t)sl * m.n_phase * NR, &S.flag);
+        if (tid == 0) {
+          S.slot_of[bd] = sl;
+          S.slot_ok[sl] = ok ? 1 : 0;
+          if (!ok) atomicOr(F.err, EFLAG_WINDOW);
         }
-        const float wi = O.w[i];
-        const float r = O.data[i] - f;
-        int k = 0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const float wa = wi * J[a];
-#pragma unroll
-          for (int bb = a; bb < 4; ++bb) {
-            out[k] = fmaf(wa, J[bb], out[k]);
-            ++k;
-          }
-          out[10 + a] = fmaf(wa, r, out[10 + a]);
-        }
-        out[14] = fmaf(r * r, wi, out[14]);
+        ++sl;
       }
-      __syncthreads();
+    }
+    __syncthreads();
+    for (int i = tid; i < O.n; i += WG) {
+      const int bd = O.band[i];
+      if ((unsigned)bd >= (unsigned)m.n_bands) continue;
+      const int slot = S.slot_of[bd];
+      if (slot < 0) continue;
+      const PhaseCell pc = phase_cell(O.t[i], t0, s64, m);
+      if (!pc.in || pc.nan) continue;
+      const int rlo = S.rlo[bd], rhi = S.rhi[bd];
+      const float* Rb = L.R + (size_t)slot * m.n_phase * NR;
+      float J[4], f;
+      if (!S.slot_ok[slot]) {
+        f = __builtin_nanf("");
+        J[0] = J[1] = J[2] = J[3] = f;
+      } else {
+        float wp[4], dw[4];
+        cr_weights(pc.x, pc.edge, wp);
+        cr_dweights(pc.x, pc.edge, dw);
+        const int tb0 = pc.edge ? 1 : 0, tb1 = pc.edge ? 3 : 4;
+        float Sx = 0.f, Sp = 0.f, S1 = 0.f, Sc = 0.f;
+        for (int t = tb0; t < tb1; ++t) {
+          const float* r = Rb + row_clamp(pc.a - 1 + t, rlo, rhi) * NR;
+          Sx = fmaf(wp[t], r[0], Sx);
+          Sp = fmaf(dw[t], r[0], Sp);
+          S1 = fmaf(wp[t], r[1], S1);
+          Sc = fmaf(wp[t], r[2], Sc);
+        }
+        f = A * Sx;
+        J[0] = -A * s * Sp * m.inv_dphase;   // d/dt0
+        J[1] = f;                            // d/d ln x0
+        J[2] = A * S1;                       // d/dx1
+        J[3] = A * Sc;                       // d/dc
+      }
+      const float wi = O.w[i];
+      const float r = O.data[i] - f;
+      int k = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const float wa = wi * J[a];
+#pragma unroll
+        for (int bb = a; bb < 4; ++bb) {
+          out[k] = fmaf(wa, J[bb], out[k]);
+          ++k;
+        }
+        out[10 + a] = fmaf(wa, r, out[10 + a]);
+      }
+      out[14] = fmaf(r * r, wi, out[14]);
+    }
+    __syncthreads();
+    for (int h = 0; h < 2; ++h) {
+      unsigned gm = h ? g1 : g0;
+      while (gm) {
+        const int bd = h * 32 + __ffs(gm) - 1;
+        gm &= gm - 1;
+        if (tid == 0) S.slot_of[bd] = -1;
+      }
     }
   }
   block_sum<15>(out, S.red);
@@ -158,7 +184,7 @@ __device__ bool damped_solve(const float* H, const float* g, float lambda, float
 __global__ __launch_bounds__(WG) void k_fit(KModel m, KTables tb, KFit F) {
   extern __shared__ __align__(16) char smem[];
   __shared__ FitShared S;
-  const Lds L = lds_carve<FIT>(smem, m, tb.max_pts);
+  const Lds L = lds_carve<FIT>(smem, m, tb);
   const int tid = threadIdx.x;
   FitSlot* sl = F.slots + F.active[blockIdx.x];
   const int adm = uni(F.admit[blockIdx.x]);
@@ -280,13 +306,13 @@ __global__ __launch_bounds__(WG) void k_fit(KModel m, KTables tb, KFit F) {
   }
 }
 
-size_t fit_lds_bytes(const KModel& m, int max_pts) {
-  return lds_layout_bytes<FIT>(m.n_phase, m.n_wave, max_pts);
+size_t fit_lds_bytes(const KModel& m, int max_pts, int jcap) {
+  return lds_layout_bytes<FIT>(m.n_phase, max_pts, jcap);
 }
 
 hipError_t launch_fit(const KModel& m, const KTables& tb, const KFit& f, hipStream_t st) {
   if (f.n_active <= 0) return hipSuccess;
-  const size_t lds = fit_lds_bytes(m, tb.max_pts);
+  const size_t lds = fit_lds_bytes(m, tb.max_pts, tb.jcap);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_fit, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

@@ -241,9 +241,14 @@ sb_status sb_add_band(sb_ctx* ctx, const double* wave, const double* trans, int3
   sb_status st = sbh::build_band_grid(wave, trans, n, ctx->cfg.max_spacing, lam, W);
   if (st != SB_OK) return st;
   const int np = (int)lam.size();
+  // surface window of the band for rest wavelengths lam/(1+z), z > -1/2: at most 2 (U - L)/dwave
+  // columns plus the stencil
+  const double span = wave[n - 1] - wave[0];
+  const int jc = (int)std::min<double>(ctx->km.n_wave + 4, std::ceil(2.0 * span * ctx->km.inv_dwave_d) + 8);
+  const int jcap = std::max(ctx->jcap, jc);
   // the per-supernova pipeline keeps a band's nodes in LDS: check it fits
-  const size_t need = std::max(sbk::lds_bytes(ctx->km, std::max(np, ctx->max_pts), true),
-                               sbk::fit_lds_bytes(ctx->km, std::max(np, ctx->max_pts)));
+  const size_t need = std::max(sbk::lds_bytes(ctx->km, std::max(np, ctx->max_pts), jcap, true),
+                               sbk::fit_lds_bytes(ctx->km, std::max(np, ctx->max_pts), jcap));
   if (need > ctx->max_lds) return set_error(SB_ERR_ARG, "sb_add_band: band grid too large for LDS");
   std::vector<float2> host(np);
   for (int k = 0; k < np; ++k) host[k] = make_float2((float)lam[k], (float)W[k]);
@@ -257,6 +262,7 @@ sb_status sb_add_band(sb_ctx* ctx, const double* wave, const double* trans, int3
   ctx->band_lo.push_back(wave[0]);
   ctx->band_hi.push_back(wave[n - 1]);
   ctx->max_pts = std::max(ctx->max_pts, np);
+  ctx->jcap = jcap;
   ctx->n_bands = id + 1;
   ctx->km.n_bands = ctx->n_bands;
   *band_id = id;
@@ -297,7 +303,7 @@ static sbk::KBatch make_kbatch(sb_ctx* ctx, const sb_batch* b) {
 static sb_status launch(sb_ctx* ctx, bool adj, sbk::KBatch& kb, hipStream_t st) {
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  const size_t lds = sbk::lds_bytes(ctx->km, ctx->max_pts, adj);
+  const size_t lds = sbk::lds_bytes(ctx->km, ctx->max_pts, ctx->jcap, adj);
   if (lds > ctx->max_lds) return set_error(SB_ERR_ARG, "bands too large for LDS");
   e = sbk::launch_sn(adj, ctx->km, ctx->tables(), kb, st);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");

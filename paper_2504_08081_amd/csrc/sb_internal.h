@@ -9,7 +9,7 @@
 
 namespace sbk {
 
-constexpr int WG = 256;            // threads per workgroup (4 wave64)
+constexpr int WG = 64;             // threads per workgroup: one wave64 per supernova
 constexpr int NWAVES = WG / 64;
 constexpr int MAX_PHASE = 256;     // surface rows supported
 constexpr int MAX_WAVE = 8192;     // surface columns supported
@@ -34,6 +34,7 @@ struct KTables {
   const float2* pts;    // [n_bands][SB_MAX_BAND_POINTS] of (lam_k, W_k)
   const int* npts;      // [n_bands] node count per band
   int max_pts;          // largest node count over registered bands (sizes the LDS)
+  int jcap;             // largest surface window (columns) a band can need for z > -1/2
 };
 
 // One bandflux / adjoint launch.
@@ -49,7 +50,7 @@ struct KBatch {
 };
 
 // Dynamic LDS bytes of the per-supernova pipeline.
-size_t lds_bytes(const KModel& m, int max_pts, bool adj);
+size_t lds_bytes(const KModel& m, int max_pts, int jcap, bool adj);
 
 // One workgroup per supernova, or per parameter sample when the batch shares
 // one observation table (forward, or forward + adjoint).
@@ -107,6 +108,6 @@ struct KFit {
 };
 
 hipError_t launch_fit(const KModel& m, const KTables& tb, const KFit& f, hipStream_t st);
-size_t fit_lds_bytes(const KModel& m, int max_pts);
+size_t fit_lds_bytes(const KModel& m, int max_pts, int jcap);
 
 }  // namespace sbk

@@ -1,6 +1,7 @@
 """CPU check of the compiled gfx950 kernels (no GPU needed): every loop that holds a
 barrier has uniform (scalar) loop control, so no wave can be split around a barrier."""
 import os
+import re
 
 import pytest
 
@@ -13,7 +14,10 @@ CSRC = os.path.join(ROOT, "paper_2504_08081_amd", "csrc")
 @pytest.mark.parametrize("src", ["sb_bandflux.hip", "sb_fit.hip"])
 def test_no_barrier_in_per_lane_loop(src, tmp_path):
     asm = device_asm(os.path.join(CSRC, src), str(tmp_path / "k.s"))
-    assert "s_barrier" in asm
+    if "s_barrier" not in asm:
+        # one-wave workgroups: the compiler drops the barriers altogether
+        sizes = set(int(v) for v in re.findall(r"\.max_flat_workgroup_size:\s+(\d+)", asm))
+        assert sizes and max(sizes) <= 64, sizes
     bad = per_lane_loops_with_barrier(asm)
     assert bad == [], f"loops holding a barrier with per-lane control: {bad}"
 
