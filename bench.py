@@ -6,8 +6,9 @@ A step is one pass of the whole hot path over the 4,096-supernova batch
 observation, chi-square against noisy data, and the hand-written adjoint giving
 d chi2 / d(z, t0, x0, x1, c) per supernova (one fused launch).  `value` is
 observations evaluated per second (forward + adjoint) with all inputs resident
-in HBM.  Extra legs report the forward-only kernel, the persistent sweep
-(1,048,576 parameter samples x 120 observations) against the plain kernel on the
+in HBM.  Extra legs report the forward-only kernel, the broadcast sweep
+(1,048,576 parameter samples x 120 observations, one observation table broadcast to
+every sample) against the plain kernel on the
 same work, the 65,536 x 100 forward + adjoint batch, and the fit server under
 Poisson load (p50/p99 latency).  The FP64 oracle is timed on the host cores on a
 bounded sample as `cpu_baseline`.
@@ -157,6 +158,40 @@ def cpu_baseline(batch, model, bands, budget_s):
                       f"{batch.n_sn} supernovae ({done_obs} observations) in {dt:.1f} s, {cores} worker processes"}
 
 
+# ----------------------------------------------------------------------------- HBM traffic from counters
+
+PROFILE_VJP = os.path.join(ROOT, "profiles", "k_sn_vjp_4096sn.md")
+
+
+def kernel_sources_sha256():
+    """Hash of the device sources (kernels and the headers they include)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2504_08081_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(path):
+    """HBM bytes per launch recorded with the rocprofv3 FETCH_SIZE / WRITE_SIZE passes, or None if
+    there is no record or the kernels have changed since it was taken."""
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            k, _, v = line.partition(":")
+            if k.strip() in ("kernel_sources_sha256", "traffic_bytes_per_launch"):
+                rec[k.strip()] = v.strip()
+    if rec.get("kernel_sources_sha256") != kernel_sources_sha256() or "traffic_bytes_per_launch" not in rec:
+        return None
+    return int(rec["traffic_bytes_per_launch"])
+
+
 # ----------------------------------------------------------------------------- timing helpers
 
 def time_launches(torch, fn, steps, warmup):
@@ -254,7 +289,7 @@ def main():
         "config": {"workload": "fwd+adjoint chi2 gradient, 4096 SN, uneven 20-200 obs, 6 bands (configs 2/3)",
                    "n_sn": truth.n_sn, "n_obs": n_obs, "bands": 6, "surface": "71x721", "parallelism": "none"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": profiled_traffic(PROFILE_VJP),
                      "kernel": "k_sn<VJP>", "kernel_ms": float(durs.mean()),
                      "flops_per_launch": flops, "work": st},
         "reference_count_tflops": reference_flops(st, "vjp") / kern_s / 1e12,
@@ -310,9 +345,9 @@ def main():
         same = bool(torch.equal(chi, chi_pl))
         del tt, bb, off, dd, ww
         evals = n * no
-        result["sweep"] = {"samples": n, "obs": no, "persistent_evals_per_s": evals / (d_sw.mean() * 1e-3),
+        result["sweep"] = {"samples": n, "obs": no, "broadcast_evals_per_s": evals / (d_sw.mean() * 1e-3),
                            "plain_evals_per_s": evals / (d_pl.mean() * 1e-3),
-                           "persistent_ms": float(d_sw.mean()), "plain_ms": float(d_pl.mean()),
+                           "broadcast_ms": float(d_sw.mean()), "plain_ms": float(d_pl.mean()),
                            "bitwise_equal": same}
         log(f"sweep: {result['sweep']}")
 

@@ -127,7 +127,11 @@ enum {
 };
 
 /* A batch of supernovae in structure-of-arrays layout, all device pointers.
- * Supernova s has parameters z[s], t0[s], x0[s], x1[s], c[s] (z > -1).
+ * Supernova s has parameters z[s], t0[s], x0[s], x1[s], c[s] (z > -1).  A band
+ * whose rest-frame window lam/(1+z) leaves the surface's wavelength grid, or
+ * (only possible for z < -1/4) spans more surface columns than the context
+ * sized its LDS for, cannot be evaluated: its observations give NaN and the
+ * device flag that sb_device_check reports as SB_ERR_RANGE is set.
  * Without SB_OBS_BROADCAST its observations are i in [sn_offsets[s], sn_offsets[s+1])
  * (CSR, non-decreasing, sn_offsets[0] = 0, sn_offsets[n_sn] = n_obs), at time t[i]
  * (days, same origin as t0) through band band[i].  With SB_OBS_BROADCAST,
@@ -144,9 +148,9 @@ typedef struct {
 
 /* Bandflux of every observation (the bandflux equation).
  * out: [n_obs] fluxes; with SB_OBS_BROADCAST [n_sn][n_obs]; with SB_OUT_CHI2
- * [n_sn] chi2_s = sum_i (f_i - data_i)^2 inv_sigma2_i.  One workgroup per
- * supernova, or, with SB_OBS_BROADCAST, a persistent grid that takes samples
- * from a work counter and keeps the observation table in LDS. */
+ * [n_sn] chi2_s = sum_i (f_i - data_i)^2 inv_sigma2_i.  One single-wave
+ * workgroup per supernova, or, with SB_OBS_BROADCAST, per parameter sample
+ * (every sample reads the one shared observation table). */
 sb_status sb_bandflux(sb_ctx *ctx, const sb_batch *batch, float *out, void *hip_stream);
 
 /* Forward pass plus adjoint: grad[s*5 + q] = sum_i gbar_i d f_i / d theta_s[q],

@@ -105,7 +105,7 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
   unsigned rem0 = (unsigned)uni((int)S.mask[0]), rem1 = (unsigned)uni((int)S.mask[1]);
   while (rem0 | rem1) {
     unsigned g0, g1;
-    take_group(rem0, rem1, g0, g1);
+    take_group(rem0, rem1, g0, g1, ModeInfo<MODE>::GROUP);
     // row projections of every band of the group
     int sl = 0;
     for (int h = 0; h < 2; ++h) {

@@ -47,12 +47,15 @@ enum Mode { FWD = 0, FIT = 1, VJP = 2 };
 //   FIT: G, Gc              | Rx, R1, Rc
 //   VJP: G, Gc, Glc, Gd     | Rx, R1, Rc, Rl
 template <int MODE> struct ModeInfo;
-template <> struct ModeInfo<FWD> { static constexpr int NG = 1, NR = 1; typedef float V; };
-template <> struct ModeInfo<FIT> { static constexpr int NG = 2, NR = 3; typedef float2 V; };
-template <> struct ModeInfo<VJP> { static constexpr int NG = 4, NR = 4; typedef float4 V; };
+// GROUP bands have their row projections held in LDS at once, and the
+// observations of those bands are finished in one pass; a smaller group keeps
+// the larger adjoint projections within a footprint that lets more waves share
+// a compute unit (an extra group costs one more scan of the band ids).
+template <> struct ModeInfo<FWD> { static constexpr int NG = 1, NR = 1, GROUP = 8; typedef float V; };
+template <> struct ModeInfo<FIT> { static constexpr int NG = 2, NR = 3, GROUP = 4; typedef float2 V; };
+template <> struct ModeInfo<VJP> { static constexpr int NG = 4, NR = 4, GROUP = 3; typedef float4 V; };
 
-// Bands whose row projections are held at once; the observations of a group
-// are finished in one pass.
+// Largest group over the modes (sizes the per-slot flags).
 constexpr int BAND_GROUP = 8;
 
 // Catmull-Rom (Keys a = -1/2) weights of the four nodes a-1..a+2 at fraction x of
@@ -147,7 +150,7 @@ struct Lds {
   int* j0;     // [max_pts]                  wavelength cell per point
   int* kf;     // [jcap + 2]                 first point of each cell
   void* G;     // [jcap] of V                weight vectors over the window
-  float* R;    // [BAND_GROUP][n_phase][NR]  row projections of the bands of a group
+  float* R;    // [GROUP][n_phase][NR]       row projections of the bands of a group
 };
 
 template <int MODE>
@@ -161,7 +164,7 @@ __host__ __device__ inline size_t lds_layout_bytes(int n_phase, int max_pts, int
   b += (size_t)(jcap + 2) * sizeof(int);
   b = (b + 15) & ~(size_t)15;
   b += (size_t)jcap * sizeof(V);
-  b += (size_t)BAND_GROUP * n_phase * NR * sizeof(float);
+  b += (size_t)ModeInfo<MODE>::GROUP * n_phase * NR * sizeof(float);
   return b;
 }
 
@@ -228,6 +231,52 @@ __device__ inline void gather_cell(typename ModeInfo<MODE>::V& g, const Lds& L, 
   }
 }
 
+// Surface nodes (M0, M1) of the lane's row in 8 consecutive columns: buffer
+// loads with the lane's row offset loff in a vector register and the column's
+// byte offset col (uniform) in a scalar register, so no vector address
+// arithmetic is spent.  The resource's size bounds every read.
+__device__ inline void load_cols8(float2 (&v)[8], __amdgpu_buffer_rsrc_t rs, unsigned loff, int col, int cstride) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+    v[u] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)loff, col + u * cstride, 0));
+}
+
+// One window column of the row projections: node mc = (M0, M1) of the lane's
+// row, the next column's node mn (for the difference), weight vector g.
+template <int MODE>
+__device__ inline void col_step(float (&acc)[4], typename ModeInfo<MODE>::V g, float2 mc, float2 mn, float x1) {
+  const float mx = fmaf(x1, mc.y, mc.x);
+  if constexpr (MODE == FWD) {
+    acc[0] = fmaf(g, mx, acc[0]);
+  } else {
+    acc[0] = fmaf(g.x, mx, acc[0]);
+    acc[1] = fmaf(g.x, mc.y, acc[1]);
+    acc[2] = fmaf(g.y, mx, acc[2]);
+    if constexpr (MODE == VJP) {
+      const float dx = fmaf(x1, mn.y - mc.y, mn.x - mc.x);
+      acc[3] = fmaf(g.z, mx, acc[3]);
+      acc[3] = fmaf(g.w, dx, acc[3]);
+    }
+  }
+}
+
+// Eight columns held in v; nx is the column after them.  Column u goes to chain u mod 4.
+template <int MODE>
+__device__ inline void chunk8(float (&acc)[4][4], const typename ModeInfo<MODE>::V* g, const float2 (&v)[8],
+                              float2 nx, float x1) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) col_step<MODE>(acc[u & 3], g[u], v[u], u < 7 ? v[u + 1] : nx, x1);
+}
+
+// The last rem (< 8, uniform) columns, held in v[0..rem-1]; v[rem] is the column after them.
+template <int MODE>
+__device__ inline void tail_cols(float (&acc)[4][4], const typename ModeInfo<MODE>::V* g, const float2 (&v)[8],
+                                 int rem, float x1) {
+#pragma unroll
+  for (int u = 0; u < 7; ++u)
+    if (u < rem) col_step<MODE>(acc[u & 3], g[u], v[u], v[u + 1], x1);
+}
+
 // Row projections of one (supernova, band) for rows [rlo, rhi], written to
 // Rb[a*NR + r] for the absolute row a:
 //   r=0  sum_j G(j)  (M0 + x1 M1)[a, j]
@@ -242,7 +291,7 @@ __device__ inline void gather_cell(typename ModeInfo<MODE>::V& g, const Lds& L, 
 // so that r=3 gives sum_k om_k mu_k [dI/dmu + c CL' I] at the phase rows.
 // All threads of the workgroup must call it.  Returns false, uniformly, when
 // the band's rest window leaves the wavelength grid (or exceeds the window
-// capacity, which covers z > -1/2).  *flag is an LDS int used as scratch.
+// capacity, which covers z >= WINDOW_Z_MIN).  *flag is an LDS int used as scratch.
 template <int MODE>
 __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, float c, float x1,
                           int rlo, int rhi, const Lds& L, float* Rb, int* flag) {
@@ -334,87 +383,39 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   }
   __syncthreads();
 
-  // (4) row projections: lanes over rows, the wave over every window column,
-  //     accumulated in four interleaved chains (columns cc mod 4) that are added
-  //     pairwise at the end.  The column base is uniform (scalar) and the lane's
-  //     row offset is fixed, so a load needs one address add.
+  // (4) row projections: lanes over rows, the wave over every window column in
+  //     chunks of 8 columns; the loads of the next chunk are issued before the
+  //     current one is summed (two register buffers in turn).  The column address
+  //     is uniform (scalar) plus the lane's fixed row offset, and the padding
+  //     columns after the grid keep every prefetch in bounds.
   const int nrow = rhi - rlo + 1;
-  const int last = m.n_wave - 1;
+  const int cstride = m.row_pad * (int)sizeof(float2);
+  const int n8 = J >> 3, rem = J & 7;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)tb.surf, 0, tb.surf_bytes, BUF_RSRC_WORD3);
   for (int rb = 0; rb < nrow; rb += 64) {
     const int a = rlo + rb + lane;
-    const int a_ld = a < m.n_phase - 1 ? a : m.n_phase - 1;
-    const float2* col0 = tb.surf + a_ld;
+    const unsigned loff = (unsigned)(a < m.n_phase - 1 ? a : m.n_phase - 1) * (unsigned)sizeof(float2);
+    const int cb = j_lo * cstride;
     float acc[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[u][r] = 0.f;
-    if constexpr (MODE == VJP) {
-      // first differences need the next column (clamped at the grid end, where the
-      // difference weight is zero)
-      float2 cur = col0[(size_t)j_lo * m.row_pad];
-      int cc = 0;
-      for (; cc + 4 <= J; cc += 4) {
-        float2 mm[5];
-        mm[0] = cur;
-#pragma unroll
-        for (int u = 1; u <= 4; ++u) mm[u] = col0[(size_t)min(j_lo + cc + u, last) * m.row_pad];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const float4 g = Gv[cc + u];
-          const float mx = fmaf(x1, mm[u].y, mm[u].x);
-          const float dx = fmaf(x1, mm[u + 1].y - mm[u].y, mm[u + 1].x - mm[u].x);
-          acc[u][0] = fmaf(g.x, mx, acc[u][0]);
-          acc[u][1] = fmaf(g.x, mm[u].y, acc[u][1]);
-          acc[u][2] = fmaf(g.y, mx, acc[u][2]);
-          acc[u][3] = fmaf(g.z, mx, acc[u][3]);
-          acc[u][3] = fmaf(g.w, dx, acc[u][3]);
-        }
-        cur = mm[4];
-      }
-      for (; cc < J; ++cc) {
-        const float2 nxt = col0[(size_t)min(j_lo + cc + 1, last) * m.row_pad];
-        const float4 g = Gv[cc];
-        const float mx = fmaf(x1, cur.y, cur.x);
-        const float dx = fmaf(x1, nxt.y - cur.y, nxt.x - cur.x);
-        acc[0][0] = fmaf(g.x, mx, acc[0][0]);
-        acc[0][1] = fmaf(g.x, cur.y, acc[0][1]);
-        acc[0][2] = fmaf(g.y, mx, acc[0][2]);
-        acc[0][3] = fmaf(g.z, mx, acc[0][3]);
-        acc[0][3] = fmaf(g.w, dx, acc[0][3]);
-        cur = nxt;
-      }
+    float2 A[8], B[8];
+    load_cols8(A, rs, loff, cb, cstride);
+    int c = 0;
+    for (; c + 2 <= n8; c += 2) {
+      load_cols8(B, rs, loff, cb + (8 * c + 8) * cstride, cstride);
+      chunk8<MODE>(acc, Gv + 8 * c, A, B[0], x1);
+      load_cols8(A, rs, loff, cb + (8 * c + 16) * cstride, cstride);
+      chunk8<MODE>(acc, Gv + 8 * c + 8, B, A[0], x1);
+    }
+    if (c < n8) {
+      load_cols8(B, rs, loff, cb + (8 * c + 8) * cstride, cstride);
+      chunk8<MODE>(acc, Gv + 8 * c, A, B[0], x1);
+      tail_cols<MODE>(acc, Gv + 8 * c + 8, B, rem, x1);
     } else {
-      int cc = 0;
-      for (; cc + 4 <= J; cc += 4) {
-        float2 mm[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) mm[u] = col0[(size_t)(j_lo + cc + u) * m.row_pad];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const V g = Gv[cc + u];
-          const float mx = fmaf(x1, mm[u].y, mm[u].x);
-          if constexpr (MODE == FWD) {
-            acc[u][0] = fmaf(g, mx, acc[u][0]);
-          } else {
-            acc[u][0] = fmaf(g.x, mx, acc[u][0]);
-            acc[u][1] = fmaf(g.x, mm[u].y, acc[u][1]);
-            acc[u][2] = fmaf(g.y, mx, acc[u][2]);
-          }
-        }
-      }
-      for (; cc < J; ++cc) {
-        const float2 mm = col0[(size_t)(j_lo + cc) * m.row_pad];
-        const V g = Gv[cc];
-        const float mx = fmaf(x1, mm.y, mm.x);
-        if constexpr (MODE == FWD) {
-          acc[0][0] = fmaf(g, mx, acc[0][0]);
-        } else {
-          acc[0][0] = fmaf(g.x, mx, acc[0][0]);
-          acc[0][1] = fmaf(g.x, mm.y, acc[0][1]);
-          acc[0][2] = fmaf(g.y, mx, acc[0][2]);
-        }
-      }
+      tail_cols<MODE>(acc, Gv + 8 * c, A, rem, x1);
     }
     if (rb + lane < nrow) {
 #pragma unroll
@@ -428,11 +429,11 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
 // Row a clamped into [rlo, rhi] (the rows whose projections were computed).
 __device__ inline int row_clamp(int a, int rlo, int rhi) { return min(max(a, rlo), rhi); }
 
-// Next group of up to BAND_GROUP bands, lowest ids first, taken out of the
-// remaining band mask (all values uniform).
-__device__ inline void take_group(unsigned& rem0, unsigned& rem1, unsigned& g0, unsigned& g1) {
+// Next group of up to cap bands, lowest ids first, taken out of the remaining
+// band mask (all values uniform).
+__device__ inline void take_group(unsigned& rem0, unsigned& rem1, unsigned& g0, unsigned& g1, int cap) {
   g0 = g1 = 0u;
-  for (int n = 0; n < BAND_GROUP && (rem0 | rem1); ++n) {
+  for (int n = 0; n < cap && (rem0 | rem1); ++n) {
     if (rem0) {
       const unsigned bit = rem0 & (0u - rem0);
       g0 |= bit;

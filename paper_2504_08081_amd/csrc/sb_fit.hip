@@ -63,7 +63,7 @@ __device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, cons
   unsigned rem0 = (unsigned)uni((int)S.mask[0]), rem1 = (unsigned)uni((int)S.mask[1]);
   while (rem0 | rem1) {
     unsigned g0, g1;
-    take_group(rem0, rem1, g0, g1);
+    take_group(rem0, rem1, g0, g1, ModeInfo<FIT>::GROUP);
     int sl = 0;
     for (int h = 0; h < 2; ++h) {
       unsigned gm = h ? g1 : g0;

@@ -195,8 +195,9 @@ sb_status sb_create(const sb_model_desc* md, const sb_config* cfg_in, int device
   c->wave_lo = md->wave0;
   c->wave_hi = md->wave0 + (md->n_wave - 1) * md->dwave;
 
-  // surfaces, wavelength-major: node (a, j) -> surf[j * row_pad + a] = (M0, M1)
-  std::vector<float2> surf((size_t)k.n_wave * k.row_pad, make_float2(0.f, 0.f));
+  // surfaces, wavelength-major: node (a, j) -> surf[j * row_pad + a] = (M0, M1), followed by
+  // SURF_PAD_COLS zero columns that the row projections may prefetch past the last column
+  std::vector<float2> surf((size_t)(k.n_wave + sbk::SURF_PAD_COLS) * k.row_pad, make_float2(0.f, 0.f));
   for (int a = 0; a < k.n_phase; ++a)
     for (int j = 0; j < k.n_wave; ++j) {
       const size_t src = (size_t)a * k.n_wave + j;
@@ -241,10 +242,11 @@ sb_status sb_add_band(sb_ctx* ctx, const double* wave, const double* trans, int3
   sb_status st = sbh::build_band_grid(wave, trans, n, ctx->cfg.max_spacing, lam, W);
   if (st != SB_OK) return st;
   const int np = (int)lam.size();
-  // surface window of the band for rest wavelengths lam/(1+z), z > -1/2: at most 2 (U - L)/dwave
-  // columns plus the stencil
+  // surface window of the band for rest wavelengths lam/(1+z), z >= WINDOW_Z_MIN: at most
+  // (U - L)/((1 + WINDOW_Z_MIN) dwave) columns plus the stencil
   const double span = wave[n - 1] - wave[0];
-  const int jc = (int)std::min<double>(ctx->km.n_wave + 4, std::ceil(2.0 * span * ctx->km.inv_dwave_d) + 8);
+  const int jc = (int)std::min<double>(ctx->km.n_wave + 4,
+                                       std::ceil(span * ctx->km.inv_dwave_d / (1.0 + sbk::WINDOW_Z_MIN)) + 8);
   const int jcap = std::max(ctx->jcap, jc);
   // the per-supernova pipeline keeps a band's nodes in LDS: check it fits
   const size_t need = std::max(sbk::lds_bytes(ctx->km, std::max(np, ctx->max_pts), jcap, true),

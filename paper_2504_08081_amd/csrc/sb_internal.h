@@ -13,6 +13,9 @@ constexpr int WG = 64;             // threads per workgroup: one wave64 per supe
 constexpr int NWAVES = WG / 64;
 constexpr int MAX_PHASE = 256;     // surface rows supported
 constexpr int MAX_WAVE = 8192;     // surface columns supported
+constexpr double WINDOW_Z_MIN = -0.25;  // the LDS window capacity covers every z >= this
+constexpr int SURF_PAD_COLS = 8;   // zero columns stored after the last surface column
+constexpr int BUF_RSRC_WORD3 = 0x00020000;  // buffer resource flags word (gfx9 family: raw 32-bit data)
 
 // Sticky device error bits (sb_device_check maps any of them to SB_ERR_RANGE).
 enum : int { EFLAG_WINDOW = 1, EFLAG_BAND = 2, EFLAG_CSR = 4 };
@@ -30,11 +33,12 @@ struct KModel {
 
 // Device tables owned by the context.
 struct KTables {
-  const float2* surf;   // [n_wave][row_pad] of (M0, M1) at node (a, j) -> surf[j*row_pad + a]
+  const float2* surf;   // [n_wave + SURF_PAD_COLS][row_pad] of (M0, M1): node (a, j) -> surf[j*row_pad + a]
   const float2* pts;    // [n_bands][SB_MAX_BAND_POINTS] of (lam_k, W_k)
   const int* npts;      // [n_bands] node count per band
   int max_pts;          // largest node count over registered bands (sizes the LDS)
-  int jcap;             // largest surface window (columns) a band can need for z > -1/2
+  int jcap;             // largest surface window (columns) a band can need for z >= WINDOW_Z_MIN
+  int surf_bytes;       // size of surf in bytes
 };
 
 // One bandflux / adjoint launch.

@@ -322,6 +322,26 @@ def test_range_errors_are_flagged(ctx6, torch, sb):
     assert np.all(np.isnan(r["grad"].cpu().numpy()))
 
 
+def test_blueshifted_window_capacity(ctx6, o6, torch, sb):
+    """Rest windows are sized for z >= -1/4: z = -0.2 matches the oracle; at z = -0.4 band 1's window
+    (about 158 columns) exceeds the capacity, which is flagged like any other range error."""
+    ctx6.device_check()
+    t = np.float32([-10.0, 0.0, 15.0, 30.0, -5.0, 5.0, 20.0])
+    band = np.int32([1, 1, 3, 3, 1, 3, 1])
+    b = synth.Batch(np.float32([-0.2]), np.float32([0.0]), np.float32([2e-5]), np.float32([0.4]),
+                    np.float32([-0.05]), t, band, np.int32([0, 7]))
+    f = ctx6.bandflux(**to_dev(b, torch)).cpu().numpy()
+    ctx6.device_check()
+    err = flux_rel_err(f, o6.bandflux(b), b.sn_offsets)
+    assert err.max() <= FLUX_TOL, err
+    b2 = synth.Batch(np.float32([-0.4]), np.float32([0.0]), np.float32([2e-5]), np.float32([0.0]),
+                     np.float32([0.0]), np.float32([0.0]), np.int32([1]), np.int32([0, 1]))
+    f2 = ctx6.bandflux(**to_dev(b2, torch)).cpu().numpy()
+    with pytest.raises(sb.SaltBFError) as e:
+        ctx6.device_check()
+    assert e.value.status == sb.SB_ERR_RANGE and np.isnan(f2[0])
+
+
 def test_host_argument_errors(ctx6, torch, sb):
     import ctypes
     b = synth.config1()
