@@ -53,7 +53,7 @@ template <int MODE> struct ModeInfo;
 // a compute unit (an extra group costs one more scan of the band ids).
 template <> struct ModeInfo<FWD> { static constexpr int NG = 1, NR = 1, GROUP = 8; typedef float V; };
 template <> struct ModeInfo<FIT> { static constexpr int NG = 2, NR = 3, GROUP = 4; typedef float2 V; };
-template <> struct ModeInfo<VJP> { static constexpr int NG = 4, NR = 4, GROUP = 3; typedef float4 V; };
+template <> struct ModeInfo<VJP> { static constexpr int NG = 4, NR = 4, GROUP = 2; typedef float4 V; };
 
 // Largest group over the modes (sizes the per-slot flags).
 constexpr int BAND_GROUP = 8;
