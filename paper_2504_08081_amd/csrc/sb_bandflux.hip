@@ -1,13 +1,14 @@
 // Bandflux, adjoint and sweep kernels (gfx950).
 //
-// One 256-thread workgroup evaluates one supernova (or one parameter sample of
-// a sweep): it scans the supernova's observations for the bands they use and
-// the surface rows their phases touch, then per band builds the wavelength
-// weight vectors and row projections (sb_device.h) and finishes every
-// observation of that band with a 4-tap phase interpolation.  The adjoint
-// accumulates sum_i gbar_i d f_i / d theta per thread and reduces it over the
-// workgroup in a fixed order, so one writer produces each supernova's
-// gradient without atomics.
+// One workgroup of NW waves evaluates one supernova (or one parameter sample
+// of a sweep): it scans the supernova's observations for the bands they use
+// and the surface rows their phases touch, then, a group of bands at a time,
+// its waves build the bands' wavelength weight vectors and row projections
+// (sb_device.h, one band per wave at a time) and the whole workgroup finishes
+// every observation of the group's bands with a 4-tap phase interpolation.
+// The adjoint accumulates sum_i gbar_i d f_i / d theta per thread and reduces
+// it over the workgroup in a fixed order, so one writer produces each
+// supernova's gradient without atomics.
 #include <climits>
 
 #include "sb_device.h"
@@ -20,8 +21,7 @@ struct SnShared {
   int rhi[SB_MAX_BANDS];
   int slot_of[SB_MAX_BANDS];   // band -> its slot in the current group, -1 otherwise
   int slot_ok[BAND_GROUP];
-  int flag;
-  float red[NWAVES * 8];
+  float red[MAX_NW * 8];
 };
 
 // Per-observation outputs of an observation that cannot be evaluated.
@@ -42,7 +42,7 @@ __device__ inline void write_obs(const KBatch& b, size_t o, float f, const float
 template <int MODE, bool BCAST>
 __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int sn, const Lds& L,
                         SnShared& S) {
-  constexpr int NR = ModeInfo<MODE>::NR;
+  constexpr int NR = ModeInfo<MODE>::NR, NW = ModeInfo<MODE>::NW, NT = NW * WAVE;
   const int tid = threadIdx.x;
   const bool chi2 = (b.flags & SB_OUT_CHI2) != 0;
   const float z = b.z[sn], t0 = b.t0[sn], x0 = b.x0[sn], x1 = b.x1[sn], c = b.c[sn];
@@ -75,7 +75,7 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
   }
 
   // scan: bands in use, rows touched; observations with nothing to integrate
-  for (int i = lo + tid; i < hi; i += WG) {
+  for (int i = lo + tid; i < hi; i += NT) {
     const int bd = b.band[i];
     const PhaseCell pc = phase_cell(b.t[i], t0, s64, m);
     const bool bad_band = (unsigned)bd >= (unsigned)m.n_bands;
@@ -106,27 +106,12 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
   while (rem0 | rem1) {
     unsigned g0, g1;
     take_group(rem0, rem1, g0, g1, ModeInfo<MODE>::GROUP);
-    // row projections of every band of the group
-    int sl = 0;
-    for (int h = 0; h < 2; ++h) {
-      unsigned gm = h ? g1 : g0;
-      while (gm) {
-        const int bd = h * 32 + __ffs(gm) - 1;
-        gm &= gm - 1;
-        const bool ok = band_rows<MODE>(m, tb, bd, s64, c, x1, uni(S.rlo[bd]), uni(S.rhi[bd]), L,
-                                        L.R + (size_t)sl * m.n_phase * NR, &S.flag);
-        if (tid == 0) {
-          S.slot_of[bd] = sl;
-          S.slot_ok[sl] = ok ? 1 : 0;
-          if (!ok) atomicOr(b.err, EFLAG_WINDOW);
-        }
-        ++sl;
-      }
-    }
+    // row projections of every band of the group, one band per wave at a time
+    group_rows<MODE>(m, tb, g0, g1, s64, c, x1, S.rlo, S.rhi, S.slot_of, S.slot_ok, L, b.err);
     __syncthreads();
 
     // every observation of the group's bands, in one pass
-    for (int i = lo + tid; i < hi; i += WG) {
+    for (int i = lo + tid; i < hi; i += NT) {
       const int bd = b.band[i];
       if ((unsigned)bd >= (unsigned)m.n_bands) continue;
       const int slot = S.slot_of[bd];
@@ -205,7 +190,7 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
   }
 
   if (MODE == VJP) {
-    block_sum<6>(acc, S.red);
+    block_sum<6, NW>(acc, S.red);
     if (tid == 0) {
 #pragma unroll
       for (int q = 0; q < 5; ++q) b.grad[(size_t)sn * SB_N_PARAMS + q] = acc[q];
@@ -213,16 +198,16 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
     }
   } else if (chi2) {
     float a1[1] = {acc[5]};
-    block_sum<1>(a1, S.red);
+    block_sum<1, NW>(a1, S.red);
     if (tid == 0) b.chi2[sn] = a1[0];
   }
 }
 
 template <int MODE, bool BCAST>
-__global__ __launch_bounds__(WG) void k_sn(KModel m, KTables tb, KBatch b) {
+__global__ __launch_bounds__(ModeInfo<MODE>::NW * WAVE) void k_sn(KModel m, KTables tb, KBatch b) {
   extern __shared__ __align__(16) char smem[];
   __shared__ SnShared S;
-  const Lds L = lds_carve<MODE>(smem, m, tb);
+  const Lds L = lds_carve<MODE>(smem, m, tb, uni((int)(threadIdx.x / WAVE)));
   sn_body<MODE, BCAST>(m, tb, b, blockIdx.x, L, S);
 }
 
@@ -242,7 +227,7 @@ static hipError_t launch_one(const KModel& m, const KTables& tb, const KBatch& b
   const size_t lds = lds_layout_bytes<MODE>(m.n_phase, tb.max_pts, tb.jcap);
   hipError_t e = prep_lds(k_sn<MODE, BCAST>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_sn<MODE, BCAST>), dim3(b.n_sn), dim3(WG), lds, st, m, tb, b);
+  hipLaunchKernelGGL((k_sn<MODE, BCAST>), dim3(b.n_sn), dim3(ModeInfo<MODE>::NW * WAVE), lds, st, m, tb, b);
   return hipGetLastError();
 }
 

@@ -47,13 +47,16 @@ enum Mode { FWD = 0, FIT = 1, VJP = 2 };
 //   FIT: G, Gc              | Rx, R1, Rc
 //   VJP: G, Gc, Glc, Gd     | Rx, R1, Rc, Rl
 template <int MODE> struct ModeInfo;
-// GROUP bands have their row projections held in LDS at once, and the
-// observations of those bands are finished in one pass; a smaller group keeps
-// the larger adjoint projections within a footprint that lets more waves share
-// a compute unit (an extra group costs one more scan of the band ids).
-template <> struct ModeInfo<FWD> { static constexpr int NG = 1, NR = 1, GROUP = 8; typedef float V; };
-template <> struct ModeInfo<FIT> { static constexpr int NG = 2, NR = 3, GROUP = 4; typedef float2 V; };
-template <> struct ModeInfo<VJP> { static constexpr int NG = 4, NR = 4, GROUP = 2; typedef float4 V; };
+// A workgroup of NW waves evaluates one supernova; the bands of a group are
+// handed to the waves in turn (wave w takes the group's bands w, w + NW, ...),
+// each wave building its bands' weight vectors in its own LDS scratch.  GROUP
+// bands have their row projections held in LDS at once, and the observations
+// of those bands are finished in one pass by the whole workgroup; a smaller
+// group keeps the larger adjoint projections within a footprint that lets more
+// waves share a compute unit (an extra group costs one more scan of the band ids).
+template <> struct ModeInfo<FWD> { static constexpr int NG = 1, NR = 1, NW = 4, GROUP = 8; typedef float V; };
+template <> struct ModeInfo<FIT> { static constexpr int NG = 2, NR = 3, NW = 4, GROUP = 8; typedef float2 V; };
+template <> struct ModeInfo<VJP> { static constexpr int NG = 4, NR = 4, NW = 2, GROUP = 4; typedef float4 V; };
 
 // Largest group over the modes (sizes the per-slot flags).
 constexpr int BAND_GROUP = 8;
@@ -143,20 +146,31 @@ __device__ inline void colour_law(float mu, const KModel& m, float& cl, float& d
   dcl = d * m.cl_inv_span;
 }
 
-// Pointers into the dynamic LDS of one workgroup (one wave, one supernova).
+// Ordering point for LDS traffic among the lanes of one wave: the wave's LDS
+// operations complete in issue order, so only the compiler must not move
+// accesses across it.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Pointers into the dynamic LDS of one workgroup (one supernova): the calling
+// wave's scratch, and the group's row projections shared by the workgroup.
 struct Lds {
   void* P;     // [max_pts] of V             weight factors per quadrature point
   float* x;    // [max_pts]                  fraction in the point's wavelength cell
   int* j0;     // [max_pts]                  wavelength cell per point
   int* kf;     // [jcap + 2]                 first point of each cell
   void* G;     // [jcap] of V                weight vectors over the window
+  int* flag;   // [1]                        range flag of the band in work
   float* R;    // [GROUP][n_phase][NR]       row projections of the bands of a group
 };
 
+// Bytes of one wave's scratch (16-byte multiple).
 template <int MODE>
-__host__ __device__ inline size_t lds_layout_bytes(int n_phase, int max_pts, int jcap) {
+__host__ __device__ inline size_t wave_scratch_bytes(int max_pts, int jcap) {
   typedef typename ModeInfo<MODE>::V V;
-  constexpr int NR = ModeInfo<MODE>::NR;
   size_t b = 0;
   b += (size_t)max_pts * sizeof(V);
   b += (size_t)max_pts * sizeof(float);
@@ -164,22 +178,30 @@ __host__ __device__ inline size_t lds_layout_bytes(int n_phase, int max_pts, int
   b += (size_t)(jcap + 2) * sizeof(int);
   b = (b + 15) & ~(size_t)15;
   b += (size_t)jcap * sizeof(V);
-  b += (size_t)ModeInfo<MODE>::GROUP * n_phase * NR * sizeof(float);
+  b += 16;
   return b;
 }
 
 template <int MODE>
-__device__ inline Lds lds_carve(char* base, const KModel& m, const KTables& tb) {
+__host__ __device__ inline size_t lds_layout_bytes(int n_phase, int max_pts, int jcap) {
+  return ModeInfo<MODE>::NW * wave_scratch_bytes<MODE>(max_pts, jcap) +
+         (size_t)ModeInfo<MODE>::GROUP * n_phase * ModeInfo<MODE>::NR * sizeof(float);
+}
+
+template <int MODE>
+__device__ inline Lds lds_carve(char* base, const KModel& m, const KTables& tb, int wave) {
   typedef typename ModeInfo<MODE>::V V;
+  const size_t ws = wave_scratch_bytes<MODE>(tb.max_pts, tb.jcap);
   Lds L;
-  size_t o = 0;
+  size_t o = (size_t)wave * ws;
   L.P = base + o;            o += (size_t)tb.max_pts * sizeof(V);
   L.x = (float*)(base + o);  o += (size_t)tb.max_pts * sizeof(float);
   L.j0 = (int*)(base + o);   o += (size_t)tb.max_pts * sizeof(int);
   L.kf = (int*)(base + o);   o += (size_t)(tb.jcap + 2) * sizeof(int);
   o = (o + 15) & ~(size_t)15;
   L.G = base + o;            o += (size_t)tb.jcap * sizeof(V);
-  L.R = (float*)(base + o);
+  L.flag = (int*)(base + o);
+  L.R = (float*)(base + (size_t)ModeInfo<MODE>::NW * ws);
   return L;
 }
 
@@ -289,15 +311,17 @@ __device__ inline void tail_cols(float (&acc)[4][4], const typename ModeInfo<MOD
 //   Glc(j) = sum_k om_k mu_k c CL'(mu_k) wl_j(mu_k),
 //   Gd(j)  = sum_k om_k mu_k e_j(mu_k) / dwave   (difference weights, D(j) = M(j+1) - M(j)),
 // so that r=3 gives sum_k om_k mu_k [dI/dmu + c CL' I] at the phase rows.
-// All threads of the workgroup must call it.  Returns false, uniformly, when
-// the band's rest window leaves the wavelength grid (or exceeds the window
-// capacity, which covers z >= WINDOW_Z_MIN).  *flag is an LDS int used as scratch.
+// Every lane of one wave calls it, with that wave's scratch in L; it
+// synchronises only within the wave.  Returns false, uniformly, when the band's
+// rest window leaves the wavelength grid (or exceeds the window capacity, which
+// covers z >= WINDOW_Z_MIN).
 template <int MODE>
 __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, float c, float x1,
-                          int rlo, int rhi, const Lds& L, float* Rb, int* flag) {
+                          int rlo, int rhi, const Lds& L, float* Rb) {
   typedef typename ModeInfo<MODE>::V V;
   constexpr int NR = ModeInfo<MODE>::NR;
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int lane = threadIdx.x & (WAVE - 1);
+  int* flag = L.flag;
   const int np = uni(tb.npts[bd]);
   bd = uni(bd);
   rlo = uni(rlo);
@@ -306,11 +330,11 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   V* Pv = (V*)L.P;
   V* Gv = (V*)L.G;
 
-  if (tid == 0) *flag = 0;
-  __syncthreads();
+  if (lane == 0) *flag = 0;
+  wave_sync();
 
   // (1) quadrature points: wavelength cell and fraction, weight factors om_k...
-  for (int k = tid; k < np; k += WG) {
+  for (int k = lane; k < np; k += WAVE) {
     const float2 lw = pts[k];
     float x, mu;
     int j0;
@@ -341,7 +365,7 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
     L.x[k] = x;
     L.j0[k] = j0;
   }
-  __syncthreads();
+  wave_sync();
   if (uni(*flag)) return false;
 
   // (2) first point of every wavelength cell touched (cells are non-decreasing in k)
@@ -351,18 +375,18 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   const int j_hi = j0l + 2 > m.n_wave - 1 ? m.n_wave - 1 : j0l + 2;
   const int J = j_hi - j_lo + 1;
   if (J > tb.jcap) return false;
-  for (int k = tid; k < np; k += WG) {
+  for (int k = lane; k < np; k += WAVE) {
     // the clamps only keep every index in bounds
     const int cur = min(max(L.j0[k] - j0f, 0), ncell - 1);
     const int prev = (k == 0) ? -1 : min(max(L.j0[k - 1] - j0f, -1), ncell - 1);
     for (int q = prev + 1; q <= cur; ++q) L.kf[q] = k;
   }
-  if (tid == 0) L.kf[ncell] = np;
-  __syncthreads();
+  if (lane == 0) L.kf[ncell] = np;
+  wave_sync();
 
   // (3) weight vectors over the window of columns [j_lo, j_hi]; node tap t and
   //     difference tap t of a point in cell j0 both land on column j0 - 1 + t
-  for (int col = tid; col < J; col += WG) {
+  for (int col = lane; col < J; col += WAVE) {
     const int j = j_lo + col;
     V g = vzero<V>();
 #define SB_GATHER_TAP(T)                                                            \
@@ -381,7 +405,7 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
 #undef SB_GATHER_TAP
     Gv[col] = g;
   }
-  __syncthreads();
+  wave_sync();
 
   // (4) row projections: lanes over rows, the wave over every window column in
   //     chunks of 8 columns; the loads of the next chunk are issued before the
@@ -422,8 +446,38 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
       for (int r = 0; r < NR; ++r) Rb[a * NR + r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
     }
   }
-  __syncthreads();
+  wave_sync();
   return true;
+}
+
+// Row projections of every band of a group (masks g0, g1; uniform), into the
+// slots 0, 1, ... of L.R in ascending band order.  Wave w takes the group's
+// bands w, w + NW, ...  Lane 0 of the wave records the band's slot and whether
+// its window could be evaluated.  All threads of the workgroup call it; the
+// caller synchronises the workgroup before the projections are read.
+template <int MODE>
+__device__ void group_rows(const KModel& m, const KTables& tb, unsigned g0, unsigned g1, double s, float c, float x1,
+                           const int* rlo, const int* rhi, int* slot_of, int* slot_ok, const Lds& L, int* err) {
+  constexpr int NR = ModeInfo<MODE>::NR, NW = ModeInfo<MODE>::NW;
+  const int wv = uni((int)(threadIdx.x / WAVE)), lane = threadIdx.x & (WAVE - 1);
+  int sl = 0;
+  for (int h = 0; h < 2; ++h) {
+    unsigned gm = h ? g1 : g0;
+    while (gm) {
+      const int bd = h * 32 + __ffs(gm) - 1;
+      gm &= gm - 1;
+      if (sl % NW == wv) {
+        const bool ok = band_rows<MODE>(m, tb, bd, s, c, x1, uni(rlo[bd]), uni(rhi[bd]), L,
+                                        L.R + (size_t)sl * m.n_phase * NR);
+        if (lane == 0) {
+          slot_of[bd] = sl;
+          slot_ok[sl] = ok ? 1 : 0;
+          if (!ok) atomicOr(err, EFLAG_WINDOW);
+        }
+      }
+      ++sl;
+    }
+  }
 }
 
 // Row a clamped into [rlo, rhi] (the rows whose projections were computed).
@@ -446,9 +500,9 @@ __device__ inline void take_group(unsigned& rem0, unsigned& rem1, unsigned& g0, 
   }
 }
 
-// Sum of N values over the workgroup in a fixed order; every thread gets the
-// same result (each thread adds the four per-wave partials in wave order).
-template <int N>
+// Sum of N values over a workgroup of NW waves in a fixed order; every thread
+// gets the same result (each thread adds the per-wave partials in wave order).
+template <int N, int NW>
 __device__ inline void block_sum(float (&v)[N], float* red) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 #pragma unroll
@@ -467,7 +521,7 @@ __device__ inline void block_sum(float (&v)[N], float* red) {
   for (int q = 0; q < N; ++q) {
     float x = red[q];
 #pragma unroll
-    for (int w2 = 1; w2 < NWAVES; ++w2) x += red[w2 * N + q];
+    for (int w2 = 1; w2 < NW; ++w2) x += red[w2 * N + q];
     v[q] = x;
   }
   __syncthreads();

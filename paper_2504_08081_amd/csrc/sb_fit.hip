@@ -1,6 +1,6 @@
 // Fit-step kernel of the serving loop (gfx950).
 //
-// One 256-thread workgroup advances one resident fit by up to `iters`
+// One workgroup of NW waves advances one resident fit by up to `iters`
 // Levenberg-Marquardt iterations.  Each evaluation runs the bandflux pipeline of
 // sb_device.h in FIT mode (row projections for the flux, d/dx1 and d/dc; d/dt0
 // comes from the phase-weight derivatives and d/d ln x0 equals the flux), and
@@ -23,8 +23,7 @@ struct FitShared {
   int rhi[SB_MAX_BANDS];
   int slot_of[SB_MAX_BANDS];
   int slot_ok[BAND_GROUP];
-  int flag;
-  float red[NWAVES * 16];
+  float red[MAX_NW * 16];
 };
 
 // chi2, H (packed) and g at parameters q = (t0, ln x0, x1, c); every thread gets them.
@@ -38,6 +37,7 @@ struct FitObs {
 
 __device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, const FitObs& O, double s64,
                          const float* q, const Lds& L, FitShared& S, float (&out)[15]) {
+  constexpr int NT = ModeInfo<FIT>::NW * WAVE;
   const int tid = threadIdx.x;
   const float t0 = q[0], x0 = expf(q[1]), x1 = q[2], c = q[3];
   const float s = (float)s64;
@@ -46,7 +46,7 @@ __device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, cons
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 15; ++k) out[k] = 0.f;
-  for (int i = tid; i < O.n; i += WG) {
+  for (int i = tid; i < O.n; i += NT) {
     const int bd = O.band[i];
     const PhaseCell pc = phase_cell(O.t[i], t0, s64, m);
     if (!pc.in || pc.nan || (unsigned)bd >= (unsigned)m.n_bands) {
@@ -64,24 +64,9 @@ __device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, cons
   while (rem0 | rem1) {
     unsigned g0, g1;
     take_group(rem0, rem1, g0, g1, ModeInfo<FIT>::GROUP);
-    int sl = 0;
-    for (int h = 0; h < 2; ++h) {
-      unsigned gm = h ? g1 : g0;
-      while (gm) {
-        const int bd = h * 32 + __ffs(gm) - 1;
-        gm &= gm - 1;
-        const bool ok = band_rows<FIT>(m, tb, bd, s64, c, x1, uni(S.rlo[bd]), uni(S.rhi[bd]), L,
-                                       L.R + (size_t)sl * m.n_phase * NR, &S.flag);
-        if (tid == 0) {
-          S.slot_of[bd] = sl;
-          S.slot_ok[sl] = ok ? 1 : 0;
-          if (!ok) atomicOr(F.err, EFLAG_WINDOW);
-        }
-        ++sl;
-      }
-    }
+    group_rows<FIT>(m, tb, g0, g1, s64, c, x1, S.rlo, S.rhi, S.slot_of, S.slot_ok, L, F.err);
     __syncthreads();
-    for (int i = tid; i < O.n; i += WG) {
+    for (int i = tid; i < O.n; i += NT) {
       const int bd = O.band[i];
       if ((unsigned)bd >= (unsigned)m.n_bands) continue;
       const int slot = S.slot_of[bd];
@@ -138,7 +123,7 @@ __device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, cons
       }
     }
   }
-  block_sum<15>(out, S.red);
+  block_sum<15, ModeInfo<FIT>::NW>(out, S.red);
 }
 
 // Solve (H + lambda diag H) d = g by Cholesky.  False if a pivot is not positive.
@@ -181,10 +166,11 @@ __device__ bool damped_solve(const float* H, const float* g, float lambda, float
   return true;
 }
 
-__global__ __launch_bounds__(WG) void k_fit(KModel m, KTables tb, KFit F) {
+__global__ __launch_bounds__(ModeInfo<FIT>::NW * WAVE) void k_fit(KModel m, KTables tb, KFit F) {
+  constexpr int NT = ModeInfo<FIT>::NW * WAVE;
   extern __shared__ __align__(16) char smem[];
   __shared__ FitShared S;
-  const Lds L = lds_carve<FIT>(smem, m, tb);
+  const Lds L = lds_carve<FIT>(smem, m, tb, uni((int)(threadIdx.x / WAVE)));
   const int tid = threadIdx.x;
   FitSlot* sl = F.slots + F.active[blockIdx.x];
   const int adm = uni(F.admit[blockIdx.x]);
@@ -196,7 +182,7 @@ __global__ __launch_bounds__(WG) void k_fit(KModel m, KTables tb, KFit F) {
   if (adm >= 0) {
     // first launch of this fit: move its observations from the inbox to the arena
     const AdmitHeader h = F.hdr[adm];
-    for (int i = tid; i < h.n_obs; i += WG) {
+    for (int i = tid; i < h.n_obs; i += NT) {
       F.t[h.arena_off + i] = F.in_t[h.src_off + i];
       F.band[h.arena_off + i] = F.in_band[h.src_off + i];
       F.data[h.arena_off + i] = F.in_data[h.src_off + i];
@@ -311,13 +297,14 @@ size_t fit_lds_bytes(const KModel& m, int max_pts, int jcap) {
 }
 
 hipError_t launch_fit(const KModel& m, const KTables& tb, const KFit& f, hipStream_t st) {
+  constexpr int NT_FIT = ModeInfo<FIT>::NW * WAVE;
   if (f.n_active <= 0) return hipSuccess;
   const size_t lds = fit_lds_bytes(m, tb.max_pts, tb.jcap);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_fit, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_fit, dim3(f.n_active), dim3(WG), lds, st, m, tb, f);
+  hipLaunchKernelGGL(k_fit, dim3(f.n_active), dim3(NT_FIT), lds, st, m, tb, f);
   return hipGetLastError();
 }
 
