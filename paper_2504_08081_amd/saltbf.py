@@ -188,6 +188,20 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+class PreparedCall:
+    """A library call whose arguments were validated and marshalled once.  Calling it launches the
+    kernel again on the same buffers and stream (the caller may update the buffers in place)."""
+    __slots__ = ("_fn", "_name", "_args", "_keep", "outputs")
+
+    def __init__(self, fn, name, args, keep, outputs):
+        self._fn, self._name, self._args, self._keep, self.outputs = fn, name, args, keep, outputs
+
+    def __call__(self):
+        st = self._fn(*self._args)
+        if st < 0:
+            _check(st, self._name)
+
+
 class Context:
     """A library context: the model surfaces and the registered bands on one GPU."""
 
@@ -299,6 +313,49 @@ class Context:
         _check(lib().sb_bandflux_vjp(self._h, ctypes.byref(b), None if chi2 else _ptr(cotangent), _ptr(grad),
                                      _ptr(flux), _ptr(jac), _ptr(c2), _stream(stream)), "sb_bandflux_vjp")
         return {"grad": grad, "flux": flux, "jac": jac, "chi2": c2}
+
+    # ------------------------------------------------------------------ prepared calls
+    def prepare_bandflux(self, z, t0, x0, x1, c, t, band, sn_offsets=None, *, broadcast=False, data=None,
+                         inv_sigma2=None, chi2=False, out=None, stream=None) -> "PreparedCall":
+        """Validate the arguments and build the call once; the returned object launches sb_bandflux on
+        the same buffers each time it is called (for loops that re-evaluate buffers updated in place)."""
+        import torch
+        b = self._batch(z, t0, x0, x1, c, t, band, sn_offsets, broadcast, data, inv_sigma2, chi2)
+        shape = (b.n_sn,) if chi2 else ((b.n_sn, b.n_obs) if broadcast else (b.n_obs,))
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=z.device)
+        _dev(out, torch.float32, "out")
+        if tuple(out.shape) != shape:
+            raise ValueError(f"out must have shape {shape}")
+        keep = (z, t0, x0, x1, c, t, band, sn_offsets, data, inv_sigma2, out)
+        return PreparedCall(lib().sb_bandflux, "sb_bandflux",
+                            (self._h, ctypes.byref(b), _ptr(out), _stream(stream)), (b, keep), {"out": out})
+
+    def prepare_bandflux_vjp(self, z, t0, x0, x1, c, t, band, sn_offsets=None, cotangent=None, *, broadcast=False,
+                             data=None, inv_sigma2=None, chi2=False, want_flux=False, want_jac=False, grad=None,
+                             stream=None) -> "PreparedCall":
+        """As prepare_bandflux, for sb_bandflux_vjp; the result buffers are in .outputs."""
+        import torch
+        b = self._batch(z, t0, x0, x1, c, t, band, sn_offsets, broadcast, data, inv_sigma2, chi2)
+        dev = z.device
+        if grad is None:
+            grad = torch.empty((b.n_sn, SB_N_PARAMS), dtype=torch.float32, device=dev)
+        _dev(grad, torch.float32, "grad")
+        if grad.numel() != b.n_sn * SB_N_PARAMS:
+            raise ValueError("grad must have n_sn * 5 elements")
+        nrow = b.n_sn * b.n_obs if broadcast else b.n_obs
+        flux = torch.empty(nrow, dtype=torch.float32, device=dev) if want_flux else None
+        jac = torch.empty((nrow, SB_N_PARAMS), dtype=torch.float32, device=dev) if want_jac else None
+        c2 = torch.empty(b.n_sn, dtype=torch.float32, device=dev) if chi2 else None
+        if not chi2:
+            _dev(cotangent, torch.float32, "cotangent")
+            if cotangent.numel() != nrow:
+                raise ValueError("cotangent has the wrong size")
+        keep = (z, t0, x0, x1, c, t, band, sn_offsets, data, inv_sigma2, cotangent)
+        outs = {"grad": grad, "flux": flux, "jac": jac, "chi2": c2}
+        args = (self._h, ctypes.byref(b), None if chi2 else _ptr(cotangent), _ptr(grad), _ptr(flux), _ptr(jac),
+                _ptr(c2), _stream(stream))
+        return PreparedCall(lib().sb_bandflux_vjp, "sb_bandflux_vjp", args, (b, keep), outs)
 
     def device_check(self, stream=None):
         """Synchronise the stream and raise if the device flagged a range error."""

@@ -194,6 +194,25 @@ def test_run_twice_bitwise(ctx6, cfg2, torch):
     assert rel < 1e-6
 
 
+def test_prepared_calls_match_plain_calls(ctx6, cfg2, torch):
+    """A prepared call launches the same kernel on the same buffers: bitwise equal to the plain call,
+    also after the parameter buffers are updated in place between launches."""
+    d = to_dev(cfg2, torch)
+    cot = torch.ones(cfg2.n_obs, dtype=torch.float32, device="cuda")
+    pv = ctx6.prepare_bandflux_vjp(**d, cotangent=cot, want_flux=True)
+    pf = ctx6.prepare_bandflux(**d)
+    for step in range(2):
+        pv()
+        pf()
+        a = ctx6.bandflux_vjp(**d, cotangent=cot, want_flux=True)
+        f = ctx6.bandflux(**d)
+        torch.cuda.synchronize()
+        assert torch.equal(pv.outputs["grad"], a["grad"]) and torch.equal(pv.outputs["flux"], a["flux"])
+        assert torch.equal(pf.outputs["out"], f)
+        d["x1"].add_(0.25)   # in-place update seen by the next launch of both prepared calls
+    ctx6.device_check()
+
+
 # ----------------------------------------------------------------------------- autograd
 
 def test_autograd_function(ctx6, torch):
