@@ -148,9 +148,9 @@ typedef struct {
 
 /* Bandflux of every observation (the bandflux equation).
  * out: [n_obs] fluxes; with SB_OBS_BROADCAST [n_sn][n_obs]; with SB_OUT_CHI2
- * [n_sn] chi2_s = sum_i (f_i - data_i)^2 inv_sigma2_i.  One single-wave
- * workgroup per supernova, or, with SB_OBS_BROADCAST, per parameter sample
- * (every sample reads the one shared observation table). */
+ * [n_sn] chi2_s = sum_i (f_i - data_i)^2 inv_sigma2_i.  One workgroup per
+ * supernova, or, with SB_OBS_BROADCAST, per parameter sample (every sample
+ * reads the one shared observation table); its waves build different bands. */
 sb_status sb_bandflux(sb_ctx *ctx, const sb_batch *batch, float *out, void *hip_stream);
 
 /* Forward pass plus adjoint: grad[s*5 + q] = sum_i gbar_i d f_i / d theta_s[q],

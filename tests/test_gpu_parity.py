@@ -383,7 +383,7 @@ def test_host_argument_errors(ctx6, torch, sb):
 # ----------------------------------------------------------------------------- sweep (workload 5)
 
 def test_sweep_matches_plain_kernel_and_oracle(ctx6, o6, torch):
-    """Persistent broadcast sweep == per-supernova kernel on the materialised batch (bitwise),
+    """Broadcast sweep == per-supernova kernel on the materialised batch (bitwise),
     and both match the oracle on sampled parameter sets."""
     sw = synth.config5a(n_samples=4096)
     smp = sw.samples
