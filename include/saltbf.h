@@ -91,6 +91,9 @@ typedef struct {
   int32_t iters_per_tick;    /* LM iterations per server launch (default 10) */
   int32_t fit_iters;         /* LM iterations per fit (default 50) */
   double lm_lambda0;         /* initial Marquardt damping (default 1e-3) */
+  int64_t lds_limit_bytes;   /* LDS a workgroup may use; 0 (default): the device's per-workgroup maximum.
+                                Kernels run several waves per workgroup where that fits, else one;
+                                bands whose one-wave form does not fit are refused by sb_add_band. */
 } sb_config;
 
 void sb_config_default(sb_config *cfg);

@@ -38,11 +38,12 @@ __device__ inline void write_obs(const KBatch& b, size_t o, float f, const float
   }
 }
 
-// Evaluate supernova (or sample) `sn`.  All threads of the workgroup call it.
-template <int MODE, bool BCAST>
+// Evaluate supernova (or sample) `sn` with a workgroup of NW waves.  All
+// threads of the workgroup call it.
+template <int MODE, bool BCAST, int NW>
 __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int sn, const Lds& L,
                         SnShared& S) {
-  constexpr int NR = ModeInfo<MODE>::NR, NW = ModeInfo<MODE>::NW, NT = NW * WAVE;
+  constexpr int NR = ModeInfo<MODE>::NR, NT = NW * WAVE;
   const int tid = threadIdx.x;
   const bool chi2 = (b.flags & SB_OUT_CHI2) != 0;
   const float z = b.z[sn], t0 = b.t0[sn], x0 = b.x0[sn], x1 = b.x1[sn], c = b.c[sn];
@@ -107,7 +108,7 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
     unsigned g0, g1;
     take_group(rem0, rem1, g0, g1, ModeInfo<MODE>::GROUP);
     // row projections of every band of the group, one band per wave at a time
-    group_rows<MODE>(m, tb, g0, g1, s64, c, x1, S.rlo, S.rhi, S.slot_of, S.slot_ok, L, b.err);
+    group_rows<MODE, NW>(m, tb, g0, g1, s64, c, x1, S.rlo, S.rhi, S.slot_of, S.slot_ok, L, b.err);
     __syncthreads();
 
     // every observation of the group's bands, in one pass
@@ -203,17 +204,17 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
   }
 }
 
-template <int MODE, bool BCAST>
-__global__ __launch_bounds__(ModeInfo<MODE>::NW * WAVE) void k_sn(KModel m, KTables tb, KBatch b) {
+template <int MODE, bool BCAST, int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_sn(KModel m, KTables tb, KBatch b) {
   extern __shared__ __align__(16) char smem[];
   __shared__ SnShared S;
-  const Lds L = lds_carve<MODE>(smem, m, tb, uni((int)(threadIdx.x / WAVE)));
-  sn_body<MODE, BCAST>(m, tb, b, blockIdx.x, L, S);
+  const Lds L = lds_carve<MODE, NW>(smem, m, tb, uni((int)(threadIdx.x / WAVE)));
+  sn_body<MODE, BCAST, NW>(m, tb, b, blockIdx.x, L, S);
 }
 
 size_t lds_bytes(const KModel& m, int max_pts, int jcap, bool adj) {
-  return adj ? lds_layout_bytes<VJP>(m.n_phase, max_pts, jcap)
-             : lds_layout_bytes<FWD>(m.n_phase, max_pts, jcap);
+  return adj ? lds_layout_bytes<VJP>(m.n_phase, max_pts, jcap, 1)
+             : lds_layout_bytes<FWD>(m.n_phase, max_pts, jcap, 1);
 }
 
 template <typename K>
@@ -222,13 +223,21 @@ static hipError_t prep_lds(K kern, size_t bytes) {
   return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+template <int MODE, bool BCAST, int NW>
+static hipError_t launch_nw(const KModel& m, const KTables& tb, const KBatch& b, size_t lds, hipStream_t st) {
+  hipError_t e = prep_lds(k_sn<MODE, BCAST, NW>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_sn<MODE, BCAST, NW>), dim3(b.n_sn), dim3(NW * WAVE), lds, st, m, tb, b);
+  return hipGetLastError();
+}
+
+// The mode's preferred number of waves per workgroup when its LDS fits, else one.
 template <int MODE, bool BCAST>
 static hipError_t launch_one(const KModel& m, const KTables& tb, const KBatch& b, hipStream_t st) {
-  const size_t lds = lds_layout_bytes<MODE>(m.n_phase, tb.max_pts, tb.jcap);
-  hipError_t e = prep_lds(k_sn<MODE, BCAST>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_sn<MODE, BCAST>), dim3(b.n_sn), dim3(ModeInfo<MODE>::NW * WAVE), lds, st, m, tb, b);
-  return hipGetLastError();
+  constexpr int NW = ModeInfo<MODE>::NW;
+  const size_t lds = lds_layout_bytes<MODE>(m.n_phase, tb.max_pts, tb.jcap, NW);
+  if (lds <= (size_t)tb.lds_limit) return launch_nw<MODE, BCAST, NW>(m, tb, b, lds, st);
+  return launch_nw<MODE, BCAST, 1>(m, tb, b, lds_layout_bytes<MODE>(m.n_phase, tb.max_pts, tb.jcap, 1), st);
 }
 
 hipError_t launch_sn(bool adj, const KModel& m, const KTables& tb, const KBatch& b, hipStream_t st) {

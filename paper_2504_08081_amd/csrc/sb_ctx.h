@@ -47,6 +47,7 @@ struct sb_ctx {
     t.max_pts = max_pts;
     t.jcap = jcap;
     t.surf_bytes = (int)((size_t)(km.n_wave + sbk::SURF_PAD_COLS) * km.row_pad * sizeof(float2));
+    t.lds_limit = (int)max_lds;
     return t;
   }
 };

@@ -47,7 +47,8 @@ enum Mode { FWD = 0, FIT = 1, VJP = 2 };
 //   FIT: G, Gc              | Rx, R1, Rc
 //   VJP: G, Gc, Glc, Gd     | Rx, R1, Rc, Rl
 template <int MODE> struct ModeInfo;
-// A workgroup of NW waves evaluates one supernova; the bands of a group are
+// A workgroup of NW waves (fewer if the LDS for NW waves does not fit; see the
+// launches) evaluates one supernova; the bands of a group are
 // handed to the waves in turn (wave w takes the group's bands w, w + NW, ...),
 // each wave building its bands' weight vectors in its own LDS scratch.  GROUP
 // bands have their row projections held in LDS at once, and the observations
@@ -134,13 +135,18 @@ __device__ inline PhaseCell phase_cell(float t, float t0, double s, const KModel
   return c;
 }
 
-// Colour law CL(mu) and dCL/dmu.
+// Colour law CL(mu) and dCL/dmu.  The Horner loop runs over the fixed maximum
+// degree with a uniform guard, so the coefficients are read once into scalar
+// registers rather than per point.
 __device__ inline void colour_law(float mu, const KModel& m, float& cl, float& dcl) {
   const float r = (mu - m.cl_b) * m.cl_inv_span;
   float v = 0.f, d = 0.f;
-  for (int n = m.cl_deg - 1; n >= 0; --n) {
-    v = fmaf(v, r, m.cl[n]);
-    d = fmaf(d, r, m.dcl[n]);
+#pragma unroll
+  for (int n = SB_MAX_CL_DEGREE - 1; n >= 0; --n) {
+    if (n < m.cl_deg) {
+      v = fmaf(v, r, m.cl[n]);
+      d = fmaf(d, r, m.dcl[n]);
+    }
   }
   cl = v * r;
   dcl = d * m.cl_inv_span;
@@ -182,13 +188,14 @@ __host__ __device__ inline size_t wave_scratch_bytes(int max_pts, int jcap) {
   return b;
 }
 
+// Dynamic LDS of a workgroup of nw waves.
 template <int MODE>
-__host__ __device__ inline size_t lds_layout_bytes(int n_phase, int max_pts, int jcap) {
-  return ModeInfo<MODE>::NW * wave_scratch_bytes<MODE>(max_pts, jcap) +
+__host__ __device__ inline size_t lds_layout_bytes(int n_phase, int max_pts, int jcap, int nw) {
+  return nw * wave_scratch_bytes<MODE>(max_pts, jcap) +
          (size_t)ModeInfo<MODE>::GROUP * n_phase * ModeInfo<MODE>::NR * sizeof(float);
 }
 
-template <int MODE>
+template <int MODE, int NW>
 __device__ inline Lds lds_carve(char* base, const KModel& m, const KTables& tb, int wave) {
   typedef typename ModeInfo<MODE>::V V;
   const size_t ws = wave_scratch_bytes<MODE>(tb.max_pts, tb.jcap);
@@ -201,7 +208,7 @@ __device__ inline Lds lds_carve(char* base, const KModel& m, const KTables& tb, 
   o = (o + 15) & ~(size_t)15;
   L.G = base + o;            o += (size_t)tb.jcap * sizeof(V);
   L.flag = (int*)(base + o);
-  L.R = (float*)(base + (size_t)ModeInfo<MODE>::NW * ws);
+  L.R = (float*)(base + (size_t)NW * ws);
   return L;
 }
 
@@ -299,6 +306,45 @@ __device__ inline void tail_cols(float (&acc)[4][4], const typename ModeInfo<MOD
     if (u < rem) col_step<MODE>(acc[u & 3], g[u], v[u], v[u + 1], x1);
 }
 
+// Quadrature point k of a band, (lam_k, W_k) = lw, for a supernova with
+// s = 1/(1+z) and colour c: its wavelength cell j0 and fraction x (from FP64
+// coordinates) and its weight factors P (om_k = W_k exp(c CL(mu_k)), and per
+// mode om_k CL, om_k mu_k c CL', om_k mu_k / dwave) into the wave's scratch.
+// Sets *flag if mu_k is off the wavelength grid.
+template <int MODE>
+__device__ inline void point_setup(const KModel& m, double s, float c, float2 lw, int k, const Lds& L, int* flag) {
+  typedef typename ModeInfo<MODE>::V V;
+  float x, mu;
+  int j0;
+  bool ok;
+  {
+#pragma clang fp contract(off)
+    const double mu_d = (double)lw.x * s;
+    const double v = (mu_d - m.wave0_d) * m.inv_dwave_d;
+    ok = (v >= 0.0) && (v <= (double)(m.n_wave - 1));
+    const double vv = ok ? v : 0.0;
+    j0 = (int)floor(vv);
+    j0 = j0 < 0 ? 0 : (j0 > m.n_wave - 2 ? m.n_wave - 2 : j0);
+    x = (float)(vv - (double)j0);
+    mu = (float)mu_d;
+  }
+  if (!ok) *flag = 1;
+  float cl, dcl;
+  colour_law(mu, m, cl, dcl);
+  const float om = lw.y * expf(c * cl);
+  V* Pv = (V*)L.P;
+  if constexpr (MODE == FWD) {
+    Pv[k] = om;
+  } else if constexpr (MODE == FIT) {
+    Pv[k] = make_float2(om, om * cl);
+  } else {
+    const float omu = om * mu;
+    Pv[k] = make_float4(om, om * cl, omu * (c * dcl), omu * m.inv_dwave);
+  }
+  L.x[k] = x;
+  L.j0[k] = j0;
+}
+
 // Row projections of one (supernova, band) for rows [rlo, rhi], written to
 // Rb[a*NR + r] for the absolute row a:
 //   r=0  sum_j G(j)  (M0 + x1 M1)[a, j]
@@ -327,43 +373,23 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   rlo = uni(rlo);
   rhi = uni(rhi);
   const float2* pts = tb.pts + (size_t)bd * SB_MAX_BAND_POINTS;
-  V* Pv = (V*)L.P;
   V* Gv = (V*)L.G;
 
   if (lane == 0) *flag = 0;
   wave_sync();
 
-  // (1) quadrature points: wavelength cell and fraction, weight factors om_k...
-  for (int k = lane; k < np; k += WAVE) {
-    const float2 lw = pts[k];
-    float x, mu;
-    int j0;
-    bool ok;
-    {
-#pragma clang fp contract(off)
-      const double mu_d = (double)lw.x * s;
-      const double v = (mu_d - m.wave0_d) * m.inv_dwave_d;
-      ok = (v >= 0.0) && (v <= (double)(m.n_wave - 1));
-      const double vv = ok ? v : 0.0;
-      j0 = (int)floor(vv);
-      j0 = j0 < 0 ? 0 : (j0 > m.n_wave - 2 ? m.n_wave - 2 : j0);
-      x = (float)(vv - (double)j0);
-      mu = (float)mu_d;
+  // (1) quadrature points: wavelength cell and fraction, weight factors om_k.
+  //     Three points per lane at a time, their table loads issued together (the
+  //     index is clamped into the table; points k >= np are skipped).
+  for (int k0 = 0; k0 < np; k0 += 3 * WAVE) {
+    float2 lw[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) lw[u] = pts[min(k0 + u * WAVE + lane, np - 1)];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int k = k0 + u * WAVE + lane;
+      if (k < np) point_setup<MODE>(m, s, c, lw[u], k, L, flag);
     }
-    if (!ok) *flag = 1;
-    float cl, dcl;
-    colour_law(mu, m, cl, dcl);
-    const float om = lw.y * expf(c * cl);
-    if constexpr (MODE == FWD) {
-      Pv[k] = om;
-    } else if constexpr (MODE == FIT) {
-      Pv[k] = make_float2(om, om * cl);
-    } else {
-      const float omu = om * mu;
-      Pv[k] = make_float4(om, om * cl, omu * (c * dcl), omu * m.inv_dwave);
-    }
-    L.x[k] = x;
-    L.j0[k] = j0;
   }
   wave_sync();
   if (uni(*flag)) return false;
@@ -455,10 +481,10 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
 // bands w, w + NW, ...  Lane 0 of the wave records the band's slot and whether
 // its window could be evaluated.  All threads of the workgroup call it; the
 // caller synchronises the workgroup before the projections are read.
-template <int MODE>
+template <int MODE, int NW>
 __device__ void group_rows(const KModel& m, const KTables& tb, unsigned g0, unsigned g1, double s, float c, float x1,
                            const int* rlo, const int* rhi, int* slot_of, int* slot_ok, const Lds& L, int* err) {
-  constexpr int NR = ModeInfo<MODE>::NR, NW = ModeInfo<MODE>::NW;
+  constexpr int NR = ModeInfo<MODE>::NR;
   const int wv = uni((int)(threadIdx.x / WAVE)), lane = threadIdx.x & (WAVE - 1);
   int sl = 0;
   for (int h = 0; h < 2; ++h) {

@@ -35,9 +35,10 @@ struct FitObs {
   int n;
 };
 
+template <int NW>
 __device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, const FitObs& O, double s64,
                          const float* q, const Lds& L, FitShared& S, float (&out)[15]) {
-  constexpr int NT = ModeInfo<FIT>::NW * WAVE;
+  constexpr int NT = NW * WAVE;
   const int tid = threadIdx.x;
   const float t0 = q[0], x0 = expf(q[1]), x1 = q[2], c = q[3];
   const float s = (float)s64;
@@ -64,7 +65,7 @@ __device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, cons
   while (rem0 | rem1) {
     unsigned g0, g1;
     take_group(rem0, rem1, g0, g1, ModeInfo<FIT>::GROUP);
-    group_rows<FIT>(m, tb, g0, g1, s64, c, x1, S.rlo, S.rhi, S.slot_of, S.slot_ok, L, F.err);
+    group_rows<FIT, NW>(m, tb, g0, g1, s64, c, x1, S.rlo, S.rhi, S.slot_of, S.slot_ok, L, F.err);
     __syncthreads();
     for (int i = tid; i < O.n; i += NT) {
       const int bd = O.band[i];
@@ -123,7 +124,7 @@ __device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, cons
       }
     }
   }
-  block_sum<15, ModeInfo<FIT>::NW>(out, S.red);
+  block_sum<15, NW>(out, S.red);
 }
 
 // Solve (H + lambda diag H) d = g by Cholesky.  False if a pivot is not positive.
@@ -166,11 +167,12 @@ __device__ bool damped_solve(const float* H, const float* g, float lambda, float
   return true;
 }
 
-__global__ __launch_bounds__(ModeInfo<FIT>::NW * WAVE) void k_fit(KModel m, KTables tb, KFit F) {
-  constexpr int NT = ModeInfo<FIT>::NW * WAVE;
+template <int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F) {
+  constexpr int NT = NW * WAVE;
   extern __shared__ __align__(16) char smem[];
   __shared__ FitShared S;
-  const Lds L = lds_carve<FIT>(smem, m, tb, uni((int)(threadIdx.x / WAVE)));
+  const Lds L = lds_carve<FIT, NW>(smem, m, tb, uni((int)(threadIdx.x / WAVE)));
   const int tid = threadIdx.x;
   FitSlot* sl = F.slots + F.active[blockIdx.x];
   const int adm = uni(F.admit[blockIdx.x]);
@@ -230,7 +232,7 @@ __global__ __launch_bounds__(ModeInfo<FIT>::NW * WAVE) void k_fit(KModel m, KTab
   const double s64 = 1.0 / (1.0 + (double)z);
   float out[15];
   if (uni(iter < 0 ? 1 : 0)) {
-    fit_eval(m, tb, F, O, s64, q, L, S, out);
+    fit_eval<NW>(m, tb, F, O, s64, q, L, S, out);
     if (uni(isfinite(out[14]) ? 1 : 0)) {
 #pragma unroll
       for (int k = 0; k < 10; ++k) H[k] = out[k];
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(ModeInfo<FIT>::NW * WAVE) void k_fit(KModel m, KTab
     float qt[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) qt[k] = q[k] + d[k];
-    fit_eval(m, tb, F, O, s64, qt, L, S, out);
+    fit_eval<NW>(m, tb, F, O, s64, qt, L, S, out);
     if (uni((isfinite(out[14]) && out[14] < chi2) ? 1 : 0)) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) q[k] = qt[k];
@@ -293,19 +295,26 @@ __global__ __launch_bounds__(ModeInfo<FIT>::NW * WAVE) void k_fit(KModel m, KTab
 }
 
 size_t fit_lds_bytes(const KModel& m, int max_pts, int jcap) {
-  return lds_layout_bytes<FIT>(m.n_phase, max_pts, jcap);
+  return lds_layout_bytes<FIT>(m.n_phase, max_pts, jcap, 1);
 }
 
-hipError_t launch_fit(const KModel& m, const KTables& tb, const KFit& f, hipStream_t st) {
-  constexpr int NT_FIT = ModeInfo<FIT>::NW * WAVE;
-  if (f.n_active <= 0) return hipSuccess;
-  const size_t lds = fit_lds_bytes(m, tb.max_pts, tb.jcap);
+template <int NW>
+static hipError_t launch_fit_nw(const KModel& m, const KTables& tb, const KFit& f, size_t lds, hipStream_t st) {
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_fit, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void*)k_fit<NW>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_fit, dim3(f.n_active), dim3(NT_FIT), lds, st, m, tb, f);
+  hipLaunchKernelGGL(k_fit<NW>, dim3(f.n_active), dim3(NW * WAVE), lds, st, m, tb, f);
   return hipGetLastError();
+}
+
+// The preferred number of waves per fit when its LDS fits, else one.
+hipError_t launch_fit(const KModel& m, const KTables& tb, const KFit& f, hipStream_t st) {
+  if (f.n_active <= 0) return hipSuccess;
+  constexpr int NW = ModeInfo<FIT>::NW;
+  const size_t lds = lds_layout_bytes<FIT>(m.n_phase, tb.max_pts, tb.jcap, NW);
+  if (lds <= (size_t)tb.lds_limit) return launch_fit_nw<NW>(m, tb, f, lds, st);
+  return launch_fit_nw<1>(m, tb, f, fit_lds_bytes(m, tb.max_pts, tb.jcap), st);
 }
 
 }  // namespace sbk

@@ -105,6 +105,7 @@ void sb_config_default(sb_config* cfg) {
   cfg->iters_per_tick = 10;
   cfg->fit_iters = 50;
   cfg->lm_lambda0 = 1e-3;
+  cfg->lds_limit_bytes = 0;
 }
 
 sb_status sb_band_grid(const double* wave, const double* trans, int32_t n, double max_spacing, int32_t cap,
@@ -156,7 +157,7 @@ sb_status sb_create(const sb_model_desc* md, const sb_config* cfg_in, int device
   if (cfg_in) cfg = *cfg_in;
   if (!(cfg.max_spacing > 0) || cfg.max_obs_per_fit < 1 || cfg.max_obs_per_fit > 1024 || cfg.max_slots < 1 ||
       cfg.max_slots > 65536 || cfg.hbm_budget_bytes < 0 || cfg.iters_per_tick < 1 || cfg.fit_iters < 0 ||
-      !(cfg.lm_lambda0 > 0))
+      !(cfg.lm_lambda0 > 0) || cfg.lds_limit_bytes < 0)
     return set_error(SB_ERR_ARG, "sb_create: bad configuration");
 
   hipError_t e = hipSetDevice(device);
@@ -170,7 +171,11 @@ sb_status sb_create(const sb_model_desc* md, const sb_config* cfg_in, int device
   c->device = device;
   c->cfg = cfg;
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
-  c->max_lds = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
+  // per-workgroup LDS: the opt-in maximum where the device reports one (launches above 64 KiB
+  // raise the kernel's limit), capped by the configuration
+  size_t dev_lds = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
+  if (prop.sharedMemPerBlockOptin > dev_lds) dev_lds = prop.sharedMemPerBlockOptin;
+  c->max_lds = cfg.lds_limit_bytes > 0 ? std::min<size_t>(dev_lds, (size_t)cfg.lds_limit_bytes) : dev_lds;
 
   sbk::KModel& k = c->km;
   k.n_phase = md->n_phase;

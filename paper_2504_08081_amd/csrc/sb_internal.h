@@ -39,6 +39,7 @@ struct KTables {
   int max_pts;          // largest node count over registered bands (sizes the LDS)
   int jcap;             // largest surface window (columns) a band can need for z >= WINDOW_Z_MIN
   int surf_bytes;       // size of surf in bytes
+  int lds_limit;        // dynamic LDS bytes a workgroup may use (host side: picks the waves per workgroup)
 };
 
 // One bandflux / adjoint launch.
@@ -53,7 +54,8 @@ struct KBatch {
   int* err;
 };
 
-// Dynamic LDS bytes of the per-supernova pipeline.
+// Dynamic LDS bytes of the per-supernova pipeline in its smallest form (one
+// wave per workgroup); launches use more waves where they fit in tb.lds_limit.
 size_t lds_bytes(const KModel& m, int max_pts, int jcap, bool adj);
 
 // One workgroup per supernova, or per parameter sample when the batch shares
@@ -112,6 +114,6 @@ struct KFit {
 };
 
 hipError_t launch_fit(const KModel& m, const KTables& tb, const KFit& f, hipStream_t st);
-size_t fit_lds_bytes(const KModel& m, int max_pts, int jcap);
+size_t fit_lds_bytes(const KModel& m, int max_pts, int jcap);   // smallest form, as lds_bytes
 
 }  // namespace sbk

@@ -46,7 +46,7 @@ class Config(ctypes.Structure):
     _fields_ = [("max_spacing", ctypes.c_double), ("max_obs_per_fit", ctypes.c_int32),
                 ("max_slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64),
                 ("iters_per_tick", ctypes.c_int32), ("fit_iters", ctypes.c_int32),
-                ("lm_lambda0", ctypes.c_double)]
+                ("lm_lambda0", ctypes.c_double), ("lds_limit_bytes", ctypes.c_int64)]
 
 
 class Batch(ctypes.Structure):

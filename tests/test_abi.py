@@ -69,3 +69,35 @@ def test_band_grid_errors():
         sb.band_grid([0.0, 20000.0], [1.0, 1.0])   # more nodes than SB_MAX_BAND_POINTS
     lam, W = sb.band_grid([3.0, 5.0, 7.0], [0.5, 1.0, 0.25], 1.0)
     np.testing.assert_array_equal(lam, np.float32([3, 4, 5, 6, 7]))
+
+
+def test_binding_structs_match_the_c_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets of its C declaration
+    (a C program compiled against include/saltbf.h prints them)."""
+    import shutil
+    import subprocess
+    from paper_2504_08081_amd import saltbf as sb
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = [("sb_model_desc", sb.ModelDesc), ("sb_config", sb.Config), ("sb_batch", sb.Batch),
+             ("sb_fit_request", sb.FitRequest), ("sb_fit_result", sb.FitResult), ("sb_stats_t", sb.Stats)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "saltbf.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        parts = ln.split()
+        got[tuple(parts[:-1])] = int(parts[-1])
+    for cname, py in pairs:
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

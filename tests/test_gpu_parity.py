@@ -213,6 +213,53 @@ def test_prepared_calls_match_plain_calls(ctx6, cfg2, torch):
     ctx6.device_check()
 
 
+def test_single_wave_workgroups_when_lds_is_short(sb, model, bands6, cfg2, torch):
+    """With a 12 KiB LDS limit every kernel runs one wave per workgroup instead of several: the
+    per-observation results are bitwise those of the multi-wave kernels (each band's projections are
+    built by one wave either way) and the per-supernova gradient differs only by reduction order."""
+    small = sb.Context.from_model(model, bands6, lds_limit_bytes=12 * 1024)
+    full = sb.Context.from_model(model, bands6)
+    ev = synth.perturb(cfg2)
+    d = to_dev(ev, torch)
+    cot = torch.from_numpy(np.random.default_rng(11).normal(size=ev.n_obs).astype(np.float32)).cuda()
+    a = small.bandflux_vjp(**d, cotangent=cot, want_flux=True)
+    b = full.bandflux_vjp(**d, cotangent=cot, want_flux=True)
+    fa, fb = small.bandflux(**d), full.bandflux(**d)
+    small.device_check()
+    full.device_check()
+    assert torch.equal(a["flux"], b["flux"]) and torch.equal(fa, fb)
+    en = grad_norm_err(a["grad"].cpu().numpy(), b["grad"].cpu().numpy().astype(np.float64), ev.x0)
+    assert en.max() <= 1e-5, en.max()
+    small.close()
+    full.close()
+
+
+def test_many_bands_and_a_long_light_curve(sb, model, torch):
+    """Twelve bands (two forward groups, three adjoint groups per supernova) and a 1,500-observation
+    light curve (many passes of the observation loops), against the oracle."""
+    bands12 = synth.make_bands(12)
+    ctx = sb.Context.from_model(model, bands12)
+    o12 = oracle.Oracle(model, bands12)
+    g = np.random.default_rng(12)
+    n0 = 1500
+    ph = np.sort(g.uniform(-18.0, 48.0, n0))
+    t_a = np.float32(100.0 + 1.3 * ph)
+    band_a = g.integers(0, 12, n0).astype(np.int32)
+    b = synth.Batch(np.float32([0.3, 0.05]), np.float32([100.0, 50.0]), np.float32([2e-5, 1e-4]),
+                    np.float32([0.7, -1.2]), np.float32([-0.08, 0.15]),
+                    np.concatenate([t_a, np.float32([52.0, 60.0, 71.0])]),
+                    np.concatenate([band_a, np.int32([11, 0, 5])]), np.int32([0, n0, n0 + 3]))
+    cot = g.normal(size=b.n_obs).astype(np.float32)
+    f, J, grad = run_jac(ctx, b, torch, cot)
+    f64, J64 = o12.jac(b)
+    g64 = oracle.segment_sum(cot.astype(np.float64)[:, None] * J64, b.sn_offsets)
+    assert flux_rel_err(f, f64, b.sn_offsets).max() <= FLUX_TOL
+    assert jac_rel_err(J, J64, x0_per_obs(b), b.sn_offsets).max() <= GRAD_TOL
+    assert grad_norm_err(grad, g64, b.x0).max() <= GRAD_TOL
+    assert flux_rel_err(run_fwd(ctx, b, torch), f64, b.sn_offsets).max() <= FLUX_TOL
+    ctx.close()
+
+
 # ----------------------------------------------------------------------------- autograd
 
 def test_autograd_function(ctx6, torch):

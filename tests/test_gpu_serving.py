@@ -90,6 +90,25 @@ def test_fits_match_oracle(sb, o6, model, bands6, requests):
     ctx.close()
 
 
+def test_fits_with_single_wave_workgroups(sb, o6, model, bands6, requests):
+    """A 12 KiB LDS limit makes the fit kernel run one wave per fit; fits still match the oracle."""
+    ctx = sb.Context.from_model(model, bands6, lds_limit_bytes=12 * 1024)
+    items = requests[:6]
+    res = run_all(ctx, items)
+    fo = oracle.FitOracle(o6)
+    for (r, d, sig, w), g in zip(items, res):
+        assert g.status == sb.SB_OK and g.iters == 50
+        ref = fo.fit(single_batch(r), r.z, r.theta_init, d, w)
+        th = ref["theta"]
+        q64 = np.array([th[0], np.log(th[1]), th[2], th[3]])
+        qg = np.array([g.t0, np.log(g.x0), g.x1, g.c])
+        _, H, _ = fo.evaluate(single_batch(r), r.z, q64, d, w)
+        sig_q = np.sqrt(np.diag(np.linalg.inv(H)))
+        assert (np.abs(qg - q64) / sig_q).max() <= 1e-2
+        assert abs(g.chi2 - ref["chi2"]) <= 1e-4 * ref["chi2"]
+    ctx.close()
+
+
 def test_alone_vs_in_the_mix_bitwise(sb, model, bands6, requests):
     """A fit alone and the same fit among 30 others sharing its launches give identical results."""
     ctx = sb.Context.from_model(model, bands6)
