@@ -306,6 +306,25 @@ __device__ inline void tail_cols(float (&acc)[4][4], const typename ModeInfo<MOD
     if (u < rem) col_step<MODE>(acc[u & 3], g[u], v[u], v[u + 1], x1);
 }
 
+// Adjoint form of the row projections on the difference surface: nodes and
+// first differences (M0, M1, D0, D1) of the lane's row in 4 consecutive columns.
+__device__ inline void load_cols4d(float4 (&v)[4], __amdgpu_buffer_rsrc_t rs, unsigned loff, int col, int cstride) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    v[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)loff, col + u * cstride, 0));
+}
+
+// One window column of the adjoint's row projections from (M0, M1, D0, D1).
+__device__ inline void col_step_d(float (&acc)[4], float4 g, float4 md, float x1) {
+  const float mx = fmaf(x1, md.y, md.x);
+  const float dx = fmaf(x1, md.w, md.z);
+  acc[0] = fmaf(g.x, mx, acc[0]);
+  acc[1] = fmaf(g.x, md.y, acc[1]);
+  acc[2] = fmaf(g.y, mx, acc[2]);
+  acc[3] = fmaf(g.z, mx, acc[3]);
+  acc[3] = fmaf(g.w, dx, acc[3]);
+}
+
 // Quadrature point k of a band, (lam_k, W_k) = lw, for a supernova with
 // s = 1/(1+z) and colour c: its wavelength cell j0 and fraction x (from FP64
 // coordinates) and its weight factors P (om_k = W_k exp(c CL(mu_k)), and per
@@ -439,6 +458,52 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   //     is uniform (scalar) plus the lane's fixed row offset, and the padding
   //     columns after the grid keep every prefetch in bounds.
   const int nrow = rhi - rlo + 1;
+  if constexpr (MODE == VJP) {
+    // the adjoint reads the difference surface, 4 columns per chunk (16 bytes per lane and column)
+    const int cstride = m.row_pad * (int)sizeof(float4);
+    const int n4 = J >> 2, rem = J & 3;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)tb.surf4, 0, 2 * tb.surf_bytes, BUF_RSRC_WORD3);
+    for (int rb = 0; rb < nrow; rb += 64) {
+      const int a = rlo + rb + lane;
+      const unsigned loff = (unsigned)(a < m.n_phase - 1 ? a : m.n_phase - 1) * (unsigned)sizeof(float4);
+      const int cb = j_lo * cstride;
+      float acc[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[u][r] = 0.f;
+      float4 A[4], B[4];
+      load_cols4d(A, rs, loff, cb, cstride);
+      int c = 0;
+      for (; c + 2 <= n4; c += 2) {
+        load_cols4d(B, rs, loff, cb + (4 * c + 4) * cstride, cstride);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) col_step_d(acc[u], Gv[4 * c + u], A[u], x1);
+        load_cols4d(A, rs, loff, cb + (4 * c + 8) * cstride, cstride);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) col_step_d(acc[u], Gv[4 * c + 4 + u], B[u], x1);
+      }
+      if (c < n4) {
+        load_cols4d(B, rs, loff, cb + (4 * c + 4) * cstride, cstride);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) col_step_d(acc[u], Gv[4 * c + u], A[u], x1);
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+          if (u < rem) col_step_d(acc[u], Gv[4 * c + 4 + u], B[u], x1);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+          if (u < rem) col_step_d(acc[u], Gv[4 * c + u], A[u], x1);
+      }
+      if (rb + lane < nrow) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) Rb[a * NR + r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
+      }
+    }
+    wave_sync();
+    return true;
+  }
   const int cstride = m.row_pad * (int)sizeof(float2);
   const int n8 = J >> 3, rem = J & 7;
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)tb.surf, 0, tb.surf_bytes, BUF_RSRC_WORD3);
