@@ -135,18 +135,13 @@ __device__ inline PhaseCell phase_cell(float t, float t0, double s, const KModel
   return c;
 }
 
-// Colour law CL(mu) and dCL/dmu.  The Horner loop runs over the fixed maximum
-// degree with a uniform guard, so the coefficients are read once into scalar
-// registers rather than per point.
+// Colour law CL(mu) and dCL/dmu.
 __device__ inline void colour_law(float mu, const KModel& m, float& cl, float& dcl) {
   const float r = (mu - m.cl_b) * m.cl_inv_span;
   float v = 0.f, d = 0.f;
-#pragma unroll
-  for (int n = SB_MAX_CL_DEGREE - 1; n >= 0; --n) {
-    if (n < m.cl_deg) {
-      v = fmaf(v, r, m.cl[n]);
-      d = fmaf(d, r, m.dcl[n]);
-    }
+  for (int n = m.cl_deg - 1; n >= 0; --n) {
+    v = fmaf(v, r, m.cl[n]);
+    d = fmaf(d, r, m.dcl[n]);
   }
   cl = v * r;
   dcl = d * m.cl_inv_span;
@@ -397,19 +392,8 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   if (lane == 0) *flag = 0;
   wave_sync();
 
-  // (1) quadrature points: wavelength cell and fraction, weight factors om_k.
-  //     Three points per lane at a time, their table loads issued together (the
-  //     index is clamped into the table; points k >= np are skipped).
-  for (int k0 = 0; k0 < np; k0 += 3 * WAVE) {
-    float2 lw[3];
-#pragma unroll
-    for (int u = 0; u < 3; ++u) lw[u] = pts[min(k0 + u * WAVE + lane, np - 1)];
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int k = k0 + u * WAVE + lane;
-      if (k < np) point_setup<MODE>(m, s, c, lw[u], k, L, flag);
-    }
-  }
+  // (1) quadrature points: wavelength cell and fraction, weight factors om_k
+  for (int k = lane; k < np; k += WAVE) point_setup<MODE>(m, s, c, pts[k], k, L, flag);
   wave_sync();
   if (uni(*flag)) return false;
 

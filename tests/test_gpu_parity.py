@@ -260,6 +260,29 @@ def test_many_bands_and_a_long_light_curve(sb, model, torch):
     ctx.close()
 
 
+def test_results_do_not_depend_on_the_rest_of_the_batch(ctx6, cfg2, torch):
+    """Every supernova's flux, gradient and chi-square are bitwise the same whether it is evaluated
+    in the full 4,096-supernova batch or in a chunk of 1,000 (other neighbours, other workgroup
+    indices, a differently filled device)."""
+    ev = synth.perturb(cfg2)
+    g = np.random.default_rng(21)
+    data = g.normal(size=ev.n_obs).astype(np.float32)
+    w = np.abs(g.normal(size=ev.n_obs)).astype(np.float32)
+    run = lambda b, dd, ww: ctx6.bandflux_vjp(**to_dev(b, torch), chi2=True, data=torch.from_numpy(dd).cuda(),
+                                               inv_sigma2=torch.from_numpy(ww).cuda(), want_flux=True)
+    full = run(ev, data, w)
+    torch.cuda.synchronize()
+    for lo in range(0, ev.n_sn, 1000):
+        idx = np.arange(lo, min(ev.n_sn, lo + 1000))
+        sel = np.arange(ev.sn_offsets[lo], ev.sn_offsets[idx[-1] + 1])
+        part = run(ev.subset(idx), data[sel], w[sel])
+        torch.cuda.synchronize()
+        assert torch.equal(part["grad"], full["grad"][lo:lo + len(idx)])
+        assert torch.equal(part["chi2"], full["chi2"][lo:lo + len(idx)])
+        assert torch.equal(part["flux"], full["flux"][sel[0]:sel[-1] + 1])
+    ctx6.device_check()
+
+
 # ----------------------------------------------------------------------------- autograd
 
 def test_autograd_function(ctx6, torch):
