@@ -56,7 +56,7 @@ template <int MODE> struct ModeInfo;
 // group keeps the larger adjoint projections within a footprint that lets more
 // waves share a compute unit (an extra group costs one more scan of the band ids).
 template <> struct ModeInfo<FWD> { static constexpr int NG = 1, NR = 1, NW = 4, GROUP = 8; typedef float V; };
-template <> struct ModeInfo<FIT> { static constexpr int NG = 2, NR = 3, NW = 4, GROUP = 8; typedef float2 V; };
+template <> struct ModeInfo<FIT> { static constexpr int NG = 2, NR = 3, NW = 8, GROUP = 8; typedef float2 V; };
 template <> struct ModeInfo<VJP> { static constexpr int NG = 4, NR = 4, NW = 2, GROUP = 4; typedef float4 V; };
 
 // Largest group over the modes (sizes the per-slot flags).

@@ -10,7 +10,7 @@
 namespace sbk {
 
 constexpr int WAVE = 64;           // threads per wavefront
-constexpr int MAX_NW = 4;          // wavefronts per workgroup, at most (per mode in sb_device.h)
+constexpr int MAX_NW = 8;          // wavefronts per workgroup, at most (per mode in sb_device.h)
 constexpr int MAX_PHASE = 256;     // surface rows supported
 constexpr int MAX_WAVE = 8192;     // surface columns supported
 constexpr double WINDOW_Z_MIN = -0.25;  // the LDS window capacity covers every z >= this
