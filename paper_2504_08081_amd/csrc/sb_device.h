@@ -55,9 +55,12 @@ template <int MODE> struct ModeInfo;
 // of those bands are finished in one pass by the whole workgroup; a smaller
 // group keeps the larger adjoint projections within a footprint that lets more
 // waves share a compute unit (an extra group costs one more scan of the band ids).
-template <> struct ModeInfo<FWD> { static constexpr int NG = 1, NR = 1, NW = 4, GROUP = 8; typedef float V; };
-template <> struct ModeInfo<FIT> { static constexpr int NG = 2, NR = 3, NW = 8, GROUP = 8; typedef float2 V; };
-template <> struct ModeInfo<VJP> { static constexpr int NG = 4, NR = 4, NW = 2, GROUP = 4; typedef float4 V; };
+// CW is the column chunk of the row projections (columns whose surface loads
+// are in flight together); the adjoint reads 4-column chunks of the difference
+// surface.
+template <> struct ModeInfo<FWD> { static constexpr int NG = 1, NR = 1, NW = 4, GROUP = 8, CW = 4; typedef float V; };
+template <> struct ModeInfo<FIT> { static constexpr int NG = 2, NR = 3, NW = 8, GROUP = 8, CW = 8; typedef float2 V; };
+template <> struct ModeInfo<VJP> { static constexpr int NG = 4, NR = 4, NW = 2, GROUP = 4, CW = 4; typedef float4 V; };
 
 // Largest group over the modes (sizes the per-slot flags).
 constexpr int BAND_GROUP = 8;
@@ -255,20 +258,22 @@ __device__ inline void gather_cell(typename ModeInfo<MODE>::V& g, const Lds& L, 
   }
 }
 
-// Surface nodes (M0, M1) of the lane's row in 8 consecutive columns: buffer
+// Surface nodes (M0, M1) of the lane's row in CW consecutive columns: buffer
 // loads with the lane's row offset loff in a vector register and the column's
 // byte offset col (uniform) in a scalar register, so no vector address
-// arithmetic is spent.  The resource's size bounds every read.
-__device__ inline void load_cols8(float2 (&v)[8], __amdgpu_buffer_rsrc_t rs, unsigned loff, int col, int cstride) {
+// arithmetic is spent.  The resource's size bounds every read: lanes past the
+// last row pass loff = BUF_OFF_NONE, read zeros and fetch nothing.
+template <int CW>
+__device__ inline void load_cols(float2 (&v)[CW], __amdgpu_buffer_rsrc_t rs, unsigned loff, int col, int cstride) {
 #pragma unroll
-  for (int u = 0; u < 8; ++u)
+  for (int u = 0; u < CW; ++u)
     v[u] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)loff, col + u * cstride, 0));
 }
 
-// One window column of the row projections: node mc = (M0, M1) of the lane's
-// row, the next column's node mn (for the difference), weight vector g.
+// One window column of the forward / fit row projections: node mc = (M0, M1)
+// of the lane's row, weight vector g.
 template <int MODE>
-__device__ inline void col_step(float (&acc)[4], typename ModeInfo<MODE>::V g, float2 mc, float2 mn, float x1) {
+__device__ inline void col_step(float (&acc)[4], typename ModeInfo<MODE>::V g, float2 mc, float x1) {
   const float mx = fmaf(x1, mc.y, mc.x);
   if constexpr (MODE == FWD) {
     acc[0] = fmaf(g, mx, acc[0]);
@@ -276,29 +281,24 @@ __device__ inline void col_step(float (&acc)[4], typename ModeInfo<MODE>::V g, f
     acc[0] = fmaf(g.x, mx, acc[0]);
     acc[1] = fmaf(g.x, mc.y, acc[1]);
     acc[2] = fmaf(g.y, mx, acc[2]);
-    if constexpr (MODE == VJP) {
-      const float dx = fmaf(x1, mn.y - mc.y, mn.x - mc.x);
-      acc[3] = fmaf(g.z, mx, acc[3]);
-      acc[3] = fmaf(g.w, dx, acc[3]);
-    }
   }
 }
 
-// Eight columns held in v; nx is the column after them.  Column u goes to chain u mod 4.
-template <int MODE>
-__device__ inline void chunk8(float (&acc)[4][4], const typename ModeInfo<MODE>::V* g, const float2 (&v)[8],
-                              float2 nx, float x1) {
+// CW columns held in v; column u goes to chain u mod 4.
+template <int MODE, int CW>
+__device__ inline void chunk_cols(float (&acc)[4][4], const typename ModeInfo<MODE>::V* g, const float2 (&v)[CW],
+                                  float x1) {
 #pragma unroll
-  for (int u = 0; u < 8; ++u) col_step<MODE>(acc[u & 3], g[u], v[u], u < 7 ? v[u + 1] : nx, x1);
+  for (int u = 0; u < CW; ++u) col_step<MODE>(acc[u & 3], g[u], v[u], x1);
 }
 
-// The last rem (< 8, uniform) columns, held in v[0..rem-1]; v[rem] is the column after them.
-template <int MODE>
-__device__ inline void tail_cols(float (&acc)[4][4], const typename ModeInfo<MODE>::V* g, const float2 (&v)[8],
+// The last rem (< CW, uniform) columns, held in v[0..rem-1].
+template <int MODE, int CW>
+__device__ inline void tail_cols(float (&acc)[4][4], const typename ModeInfo<MODE>::V* g, const float2 (&v)[CW],
                                  int rem, float x1) {
 #pragma unroll
-  for (int u = 0; u < 7; ++u)
-    if (u < rem) col_step<MODE>(acc[u & 3], g[u], v[u], v[u + 1], x1);
+  for (int u = 0; u < CW - 1; ++u)
+    if (u < rem) col_step<MODE>(acc[u & 3], g[u], v[u], x1);
 }
 
 // Adjoint form of the row projections on the difference surface: nodes and
@@ -450,7 +450,7 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
         __builtin_amdgcn_make_buffer_rsrc((void*)tb.surf4, 0, 2 * tb.surf_bytes, BUF_RSRC_WORD3);
     for (int rb = 0; rb < nrow; rb += 64) {
       const int a = rlo + rb + lane;
-      const unsigned loff = (unsigned)(a < m.n_phase - 1 ? a : m.n_phase - 1) * (unsigned)sizeof(float4);
+      const unsigned loff = rb + lane < nrow ? (unsigned)a * (unsigned)sizeof(float4) : BUF_OFF_NONE;
       const int cb = j_lo * cstride;
       float acc[4][4];
 #pragma unroll
@@ -488,33 +488,34 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
     wave_sync();
     return true;
   }
+  constexpr int CW = ModeInfo<MODE>::CW;
   const int cstride = m.row_pad * (int)sizeof(float2);
-  const int n8 = J >> 3, rem = J & 7;
+  const int nc = J / CW, rem = J % CW;
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)tb.surf, 0, tb.surf_bytes, BUF_RSRC_WORD3);
   for (int rb = 0; rb < nrow; rb += 64) {
     const int a = rlo + rb + lane;
-    const unsigned loff = (unsigned)(a < m.n_phase - 1 ? a : m.n_phase - 1) * (unsigned)sizeof(float2);
+    const unsigned loff = rb + lane < nrow ? (unsigned)a * (unsigned)sizeof(float2) : BUF_OFF_NONE;
     const int cb = j_lo * cstride;
     float acc[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[u][r] = 0.f;
-    float2 A[8], B[8];
-    load_cols8(A, rs, loff, cb, cstride);
+    float2 A[CW], B[CW];
+    load_cols<CW>(A, rs, loff, cb, cstride);
     int c = 0;
-    for (; c + 2 <= n8; c += 2) {
-      load_cols8(B, rs, loff, cb + (8 * c + 8) * cstride, cstride);
-      chunk8<MODE>(acc, Gv + 8 * c, A, B[0], x1);
-      load_cols8(A, rs, loff, cb + (8 * c + 16) * cstride, cstride);
-      chunk8<MODE>(acc, Gv + 8 * c + 8, B, A[0], x1);
+    for (; c + 2 <= nc; c += 2) {
+      load_cols<CW>(B, rs, loff, cb + (CW * c + CW) * cstride, cstride);
+      chunk_cols<MODE, CW>(acc, Gv + CW * c, A, x1);
+      load_cols<CW>(A, rs, loff, cb + (CW * c + 2 * CW) * cstride, cstride);
+      chunk_cols<MODE, CW>(acc, Gv + CW * c + CW, B, x1);
     }
-    if (c < n8) {
-      load_cols8(B, rs, loff, cb + (8 * c + 8) * cstride, cstride);
-      chunk8<MODE>(acc, Gv + 8 * c, A, B[0], x1);
-      tail_cols<MODE>(acc, Gv + 8 * c + 8, B, rem, x1);
+    if (c < nc) {
+      load_cols<CW>(B, rs, loff, cb + (CW * c + CW) * cstride, cstride);
+      chunk_cols<MODE, CW>(acc, Gv + CW * c, A, x1);
+      tail_cols<MODE, CW>(acc, Gv + CW * c + CW, B, rem, x1);
     } else {
-      tail_cols<MODE>(acc, Gv + 8 * c, A, rem, x1);
+      tail_cols<MODE, CW>(acc, Gv + CW * c, A, rem, x1);
     }
     if (rb + lane < nrow) {
 #pragma unroll

@@ -14,8 +14,9 @@ constexpr int MAX_NW = 8;          // wavefronts per workgroup, at most (per mod
 constexpr int MAX_PHASE = 256;     // surface rows supported
 constexpr int MAX_WAVE = 8192;     // surface columns supported
 constexpr double WINDOW_Z_MIN = -0.25;  // the LDS window capacity covers every z >= this
-constexpr int SURF_PAD_COLS = 8;   // zero columns stored after the last surface column
+constexpr int SURF_PAD_COLS = 16;  // zero columns after the last surface column (at least the widest chunk)
 constexpr int BUF_RSRC_WORD3 = 0x00020000;  // buffer resource flags word (gfx9 family: raw 32-bit data)
+constexpr unsigned BUF_OFF_NONE = 0x40000000u;  // a buffer offset past every resource: the load returns 0
 
 // Sticky device error bits (sb_device_check maps any of them to SB_ERR_RANGE).
 enum : int { EFLAG_WINDOW = 1, EFLAG_BAND = 2, EFLAG_CSR = 4 };
