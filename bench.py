@@ -153,19 +153,42 @@ def cpu_baseline(batch, model, bands, budget_s):
     ctx = mp.get_context("fork")
     passes = 0
     t0 = time.perf_counter()
-    with ctx.Pool(cores, initializer=_init_worker) as pool:
+    pool = ctx.Pool(cores, initializer=_init_worker)
+    try:
         while True:
             for _ in pool.imap_unordered(_oracle_chunk, work):
                 pass
             passes += 1
             if time.perf_counter() - t0 >= budget_s:
                 break
+    finally:
+        pool.close()
+        pool.join()
     dt = time.perf_counter() - t0
     done_obs = passes * batch.n_obs
     return {"value": done_obs / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle forward+adjoint (chi2 gradient), {passes} full passes over the "
                       f"{batch.n_sn} supernovae ({batch.n_obs} observations each pass) in {dt:.1f} s, "
                       f"{cores} single-threaded worker processes"}
+
+
+def _cpu_baseline_child(conn, batch, model, bands, budget_s):
+    conn.send(cpu_baseline(batch, model, bands, budget_s))
+    conn.close()
+
+
+def cpu_baseline_isolated(batch, model, bands, budget_s):
+    """cpu_baseline in a child process that has exited (with its workers and any BLAS threads) before
+    this process touches the GPU, so no host load is left behind for the timed GPU legs."""
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    rx, tx = ctx.Pipe(duplex=False)
+    proc = ctx.Process(target=_cpu_baseline_child, args=(tx, batch, model, bands, budget_s))
+    proc.start()
+    tx.close()
+    res = rx.recv()
+    proc.join()
+    return res
 
 
 # ----------------------------------------------------------------------------- HBM traffic from counters
@@ -248,7 +271,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: FP64 oracle on the host cores ...")
-        cpu = cpu_baseline(ev_params, model, bands, args.cpu_seconds)
+        cpu = cpu_baseline_isolated(ev_params, model, bands, args.cpu_seconds)
         log(f"cpu baseline: {cpu['value']:.0f} evals/s on {cpu['cores']} cores")
 
     import torch
