@@ -37,13 +37,14 @@ PEAK_HBM_GBS = 8000.0
 #     exp 1, weight factors 1 (VJP 5), fraction 1 ........................ FWD 15, VJP 25
 #   per (point, tap) pair gathered into the weight vectors: tap weight 5, one FMA per
 #     weight vector (VJP: 4, plus the difference weight 4) ................ FWD 7, VJP 17
-#   per (surface row, window column) of the row projections: FWD 2 FMA = 4; VJP two
-#     differences, 2 FMA for the combined node and difference, 5 FMA = 16
+#   per (surface row, window column) of the row projections: FWD 2 FMA = 4; VJP (on the
+#     surface with precomputed first differences) 2 FMA for the combined node and
+#     difference, 5 FMA = 14
 #   per observation: phase coordinate 4, weights 10, taps 8 (VJP 40), partials and
 #     cotangent (VJP 30) .................................................. FWD 24, VJP 90
 W_PT = {"fwd": 15, "vjp": 25}
 W_TAP = {"fwd": 7, "vjp": 17}
-W_CELL = {"fwd": 4, "vjp": 16}
+W_CELL = {"fwd": 4, "vjp": 14}
 W_OBS = {"fwd": 24, "vjp": 90}
 
 
