@@ -215,48 +215,42 @@ template <> __device__ inline float vzero<float>() { return 0.f; }
 template <> __device__ inline float2 vzero<float2>() { return make_float2(0.f, 0.f); }
 template <> __device__ inline float4 vzero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
 
-// Catmull-Rom weight of tap t (node a-1+t of cell a) at fraction x; linear in edge cells.
-template <int T>
-__device__ inline float cr_tap(float x, bool edge) {
-  if (edge) return T == 1 ? 1.f - x : (T == 2 ? x : 0.f);
-  if (T == 0) return ((-0.5f * x + 1.f) * x - 0.5f) * x;
-  if (T == 1) return (1.5f * x - 2.5f) * x * x + 1.f;
-  if (T == 2) return ((-1.5f * x + 2.f) * x + 0.5f) * x;
-  return (0.5f * x - 0.5f) * x * x;
-}
-
-// Difference weight e_t of tap t (difference D(a-1+t)); edge cells use D(a) only.
-template <int T>
-__device__ inline float cr_diff_tap(float x, bool edge) {
-  if (edge) return T == 1 ? 1.f : 0.f;
-  if (T == 0) return (1.5f * x - 2.f) * x + 0.5f;
-  if (T == 1) return (-3.f * x + 3.f) * x + 0.5f;
-  if (T == 2) return (1.5f * x - 1.f) * x;
-  return 0.f;
-}
-
-// Adds the tap-T contributions of the points of cell q to the weight vector g.
-template <int MODE, int T>
-__device__ inline void gather_cell(typename ModeInfo<MODE>::V& g, const Lds& L, int k0, int k1, bool edge) {
+// Tap sums of one wavelength cell over its points k in [k0, k1):
+//   C[t] = sum_k wl_t(x_k) P_k      (node tap t lands on column cell - 1 + t)
+// and, for the adjoint's difference weights (component w), C[t].w = sum_k
+// e_t(x_k) P_k.w for t < 3 (difference D(cell - 1 + t)).
+template <int MODE>
+__device__ inline void cell_taps(typename ModeInfo<MODE>::V (&C)[4], const Lds& L, int k0, int k1, bool edge) {
   typedef typename ModeInfo<MODE>::V V;
   const V* Pv = (const V*)L.P;
   for (int k = k0; k < k1; ++k) {
     const float x = L.x[k];
-    const float w = cr_tap<T>(x, edge);
     const V p = Pv[k];
-    if constexpr (MODE == FWD) {
-      g = fmaf(p, w, g);
-    } else if constexpr (MODE == FIT) {
-      g.x = fmaf(p.x, w, g.x);
-      g.y = fmaf(p.y, w, g.y);
-    } else {
-      g.x = fmaf(p.x, w, g.x);
-      g.y = fmaf(p.y, w, g.y);
-      g.z = fmaf(p.z, w, g.z);
-      if (T < 3) g.w = fmaf(p.w, cr_diff_tap<T>(x, edge), g.w);
+    float w[4];
+    cr_weights(x, edge, w);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if constexpr (MODE == FWD) {
+        C[t] = fmaf(p, w[t], C[t]);
+      } else {
+        C[t].x = fmaf(p.x, w[t], C[t].x);
+        C[t].y = fmaf(p.y, w[t], C[t].y);
+        if constexpr (MODE == VJP) C[t].z = fmaf(p.z, w[t], C[t].z);
+      }
+    }
+    if constexpr (MODE == VJP) {
+      float e[3];
+      cr_diff_weights(x, edge, e);
+#pragma unroll
+      for (int t = 0; t < 3; ++t) C[t].w = fmaf(p.w, e[t], C[t].w);
     }
   }
 }
+
+// v from the next lane down (lane L receives lane L - 1; lane 0 its own value).
+__device__ inline float up1(float v) { return __shfl_up(v, 1, WAVE); }
+__device__ inline float2 up1(float2 v) { return make_float2(up1(v.x), up1(v.y)); }
+__device__ inline float4 up1(float4 v) { return make_float4(up1(v.x), up1(v.y), up1(v.z), up1(v.w)); }
 
 // Surface nodes (M0, M1) of the lane's row in CW consecutive columns: buffer
 // loads with the lane's row offset loff in a vector register and the column's
@@ -413,26 +407,26 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   if (lane == 0) L.kf[ncell] = np;
   wave_sync();
 
-  // (3) weight vectors over the window of columns [j_lo, j_hi]; node tap t and
-  //     difference tap t of a point in cell j0 both land on column j0 - 1 + t
-  for (int col = lane; col < J; col += WAVE) {
-    const int j = j_lo + col;
-    V g = vzero<V>();
-#define SB_GATHER_TAP(T)                                                            \
-    {                                                                               \
-      const int cell = j - (T) + 1;                                                 \
-      const int q = cell - j0f;                                                     \
-      if (q >= 0 && q < ncell) {                                                    \
-        const bool edge = (cell == 0) || (cell == m.n_wave - 2);                    \
-        gather_cell<MODE, T>(g, L, max(L.kf[q], 0), min(L.kf[q + 1], np), edge);    \
-      }                                                                             \
+  // (3) weight vectors over the window of columns [j_lo, j_hi].  Lane L of a
+  //     pass starting at column b takes column b + L and the cell just above
+  //     it, j_lo + b + L + 1, and sums the four taps of that cell's points
+  //     (each point read once).  Column b + L needs tap t of the cell t below
+  //     that one, held by lane L - t: G = C0 + up(C1 + up(C2 + up(C3))).
+  //     Passes start 3 columns early and advance by WAVE - 3, so every tap a
+  //     written column needs comes from a lane of the same pass.
+  for (int b = -3; b + 3 < J; b += WAVE - 3) {
+    const int col = b + lane;
+    const int cell = j_lo + col + 1;
+    const int q = cell - j0f;
+    V C[4] = {vzero<V>(), vzero<V>(), vzero<V>(), vzero<V>()};
+    if (q >= 0 && q < ncell) {
+      const bool edge = (cell == 0) || (cell == m.n_wave - 2);
+      cell_taps<MODE>(C, L, max(L.kf[q], 0), min(L.kf[q + 1], np), edge);
     }
-    SB_GATHER_TAP(0)
-    SB_GATHER_TAP(1)
-    SB_GATHER_TAP(2)
-    SB_GATHER_TAP(3)
-#undef SB_GATHER_TAP
-    Gv[col] = g;
+    V g = C[2] + up1(C[3]);
+    g = C[1] + up1(g);
+    g = C[0] + up1(g);
+    if (lane >= 3 && col < J) Gv[col] = g;
   }
   wave_sync();
 
