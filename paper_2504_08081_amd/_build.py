@@ -43,7 +43,25 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, OUT)
+    build_cabi_check(verbose)
     return OUT
+
+
+CABI_SRC = os.path.join(ROOT, "tests", "c_abi", "sb_cabi_check.cpp")
+CABI_EXE = os.path.join(ROOT, "tests", "c_abi", "sb_cabi_check")
+
+
+def build_cabi_check(verbose: bool = False) -> str:
+    """The plain C++ program that drives the C ABI without Python (a test helper), linked
+    against the in-tree libsaltbf.so through a relative run path."""
+    tmp = CABI_EXE + ".tmp"
+    cmd = [hipcc(), "-O2", "-std=c++17", "-Wall", "-I", INCLUDE, CABI_SRC, "-o", tmp, "-L", HERE, "-lsaltbf",
+           "-Wl,-rpath,$ORIGIN/../../paper_2504_08081_amd"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, CABI_EXE)
+    return CABI_EXE
 
 
 if __name__ == "__main__":
