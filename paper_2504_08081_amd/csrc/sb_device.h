@@ -164,10 +164,8 @@ __device__ inline void wave_sync() {
 struct Lds {
   void* P;     // [max_pts] of V             weight factors per quadrature point
   float* x;    // [max_pts]                  fraction in the point's wavelength cell
-  int* j0;     // [max_pts]                  wavelength cell per point
   int* kf;     // [jcap + 2]                 first point of each cell
   void* G;     // [jcap] of V                weight vectors over the window
-  int* flag;   // [1]                        range flag of the band in work
   float* R;    // [GROUP][n_phase][NR]       row projections of the bands of a group
 };
 
@@ -178,12 +176,10 @@ __host__ __device__ inline size_t wave_scratch_bytes(int max_pts, int jcap) {
   size_t b = 0;
   b += (size_t)max_pts * sizeof(V);
   b += (size_t)max_pts * sizeof(float);
-  b += (size_t)max_pts * sizeof(int);
   b += (size_t)(jcap + 2) * sizeof(int);
   b = (b + 15) & ~(size_t)15;
   b += (size_t)jcap * sizeof(V);
-  b += 16;
-  return b;
+  return (b + 15) & ~(size_t)15;
 }
 
 // Dynamic LDS of a workgroup of nw waves.
@@ -201,11 +197,9 @@ __device__ inline Lds lds_carve(char* base, const KModel& m, const KTables& tb, 
   size_t o = (size_t)wave * ws;
   L.P = base + o;            o += (size_t)tb.max_pts * sizeof(V);
   L.x = (float*)(base + o);  o += (size_t)tb.max_pts * sizeof(float);
-  L.j0 = (int*)(base + o);   o += (size_t)tb.max_pts * sizeof(int);
   L.kf = (int*)(base + o);   o += (size_t)(tb.jcap + 2) * sizeof(int);
   o = (o + 15) & ~(size_t)15;
-  L.G = base + o;            o += (size_t)tb.jcap * sizeof(V);
-  L.flag = (int*)(base + o);
+  L.G = base + o;
   L.R = (float*)(base + (size_t)NW * ws);
   return L;
 }
@@ -314,31 +308,41 @@ __device__ inline void col_step_d(float (&acc)[4], float4 g, float4 md, float x1
   acc[3] = fmaf(g.w, dx, acc[3]);
 }
 
-// Quadrature point k of a band, (lam_k, W_k) = lw, for a supernova with
-// s = 1/(1+z) and colour c: its wavelength cell j0 and fraction x (from FP64
-// coordinates) and its weight factors P (om_k = W_k exp(c CL(mu_k)), and per
-// mode om_k CL, om_k mu_k c CL', om_k mu_k / dwave) into the wave's scratch.
-// Sets *flag if mu_k is off the wavelength grid.
-template <int MODE>
-__device__ inline void point_setup(const KModel& m, double s, float c, float2 lw, int k, const Lds& L, int* flag) {
-  typedef typename ModeInfo<MODE>::V V;
+// Rest wavelength mu = lam s of a quadrature point and its wavelength cell j0
+// and fraction x, from FP64 coordinates (contraction off, so every call site
+// rounds identically).  ok: mu on the wavelength grid.  The cell is
+// non-decreasing in lam.
+struct WaveCell {
   float x, mu;
   int j0;
   bool ok;
-  {
+};
+
+__device__ inline WaveCell wave_cell(float lam, double s, const KModel& m) {
 #pragma clang fp contract(off)
-    const double mu_d = (double)lw.x * s;
-    const double v = (mu_d - m.wave0_d) * m.inv_dwave_d;
-    ok = (v >= 0.0) && (v <= (double)(m.n_wave - 1));
-    const double vv = ok ? v : 0.0;
-    j0 = (int)floor(vv);
-    j0 = j0 < 0 ? 0 : (j0 > m.n_wave - 2 ? m.n_wave - 2 : j0);
-    x = (float)(vv - (double)j0);
-    mu = (float)mu_d;
-  }
-  if (!ok) *flag = 1;
+  WaveCell w;
+  const double mu_d = (double)lam * s;
+  const double v = (mu_d - m.wave0_d) * m.inv_dwave_d;
+  w.ok = (v >= 0.0) && (v <= (double)(m.n_wave - 1));
+  const double vv = w.ok ? v : 0.0;
+  int j0 = (int)floor(vv);
+  j0 = j0 < 0 ? 0 : (j0 > m.n_wave - 2 ? m.n_wave - 2 : j0);
+  w.j0 = j0;
+  w.x = (float)(vv - (double)j0);
+  w.mu = (float)mu_d;
+  return w;
+}
+
+// Quadrature point k of a band, (lam_k, W_k) = lw, for a supernova with
+// s = 1/(1+z) and colour c: its fraction x and weight factors P (om_k = W_k
+// exp(c CL(mu_k)), and per mode om_k CL, om_k mu_k c CL', om_k mu_k / dwave)
+// into the wave's scratch.  Returns the point's wavelength cell.
+template <int MODE>
+__device__ inline int point_setup(const KModel& m, double s, float c, float2 lw, int k, const Lds& L) {
+  typedef typename ModeInfo<MODE>::V V;
+  const WaveCell w = wave_cell(lw.x, s, m);
   float cl, dcl;
-  colour_law(mu, m, cl, dcl);
+  colour_law(w.mu, m, cl, dcl);
   const float om = lw.y * expf(c * cl);
   V* Pv = (V*)L.P;
   if constexpr (MODE == FWD) {
@@ -346,11 +350,11 @@ __device__ inline void point_setup(const KModel& m, double s, float c, float2 lw
   } else if constexpr (MODE == FIT) {
     Pv[k] = make_float2(om, om * cl);
   } else {
-    const float omu = om * mu;
+    const float omu = om * w.mu;
     Pv[k] = make_float4(om, om * cl, omu * (c * dcl), omu * m.inv_dwave);
   }
-  L.x[k] = x;
-  L.j0[k] = j0;
+  L.x[k] = w.x;
+  return w.j0;
 }
 
 // Row projections of one (supernova, band) for rows [rlo, rhi], written to
@@ -375,7 +379,6 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   typedef typename ModeInfo<MODE>::V V;
   constexpr int NR = ModeInfo<MODE>::NR;
   const int lane = threadIdx.x & (WAVE - 1);
-  int* flag = L.flag;
   const int np = uni(tb.npts[bd]);
   bd = uni(bd);
   rlo = uni(rlo);
@@ -383,26 +386,32 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   const float2* pts = tb.pts + (size_t)bd * SB_MAX_BAND_POINTS;
   V* Gv = (V*)L.G;
 
-  if (lane == 0) *flag = 0;
-  wave_sync();
-
-  // (1) quadrature points: wavelength cell and fraction, weight factors om_k
-  for (int k = lane; k < np; k += WAVE) point_setup<MODE>(m, s, c, pts[k], k, L, flag);
-  wave_sync();
-  if (uni(*flag)) return false;
-
-  // (2) first point of every wavelength cell touched (cells are non-decreasing in k)
-  const int j0f = uni(L.j0[0]), j0l = uni(L.j0[np - 1]);
+  // the window: the cells of the first and last points (cells are non-decreasing
+  // in k, so every point is on the grid if these two are)
+  const WaveCell wf = wave_cell(pts[0].x, s, m), wl = wave_cell(pts[np - 1].x, s, m);
+  if (!uni(wf.ok && wl.ok ? 1 : 0)) return false;
+  const int j0f = uni(wf.j0), j0l = uni(wl.j0);
   const int ncell = j0l - j0f + 1;
   const int j_lo = j0f - 1 < 0 ? 0 : j0f - 1;
   const int j_hi = j0l + 2 > m.n_wave - 1 ? m.n_wave - 1 : j0l + 2;
   const int J = j_hi - j_lo + 1;
   if (J > tb.jcap) return false;
-  for (int k = lane; k < np; k += WAVE) {
-    // the clamps only keep every index in bounds
-    const int cur = min(max(L.j0[k] - j0f, 0), ncell - 1);
-    const int prev = (k == 0) ? -1 : min(max(L.j0[k - 1] - j0f, -1), ncell - 1);
-    for (int q = prev + 1; q <= cur; ++q) L.kf[q] = k;
+
+  // (1) quadrature points: fraction and weight factors into LDS; and (2) the
+  //     first point of every cell, kf[q] (cell j0f + q): a point whose cell is
+  //     above the previous point's starts the cells in between.  The previous
+  //     point's cell comes from the lane below, or for lane 0 from the last
+  //     point of the previous pass.
+  int carry = j0f - 1;
+  for (int k0 = 0; k0 < np; k0 += WAVE) {
+    const int k = k0 + lane;
+    int j0 = j0l;
+    if (k < np) j0 = point_setup<MODE>(m, s, c, pts[k], k, L);
+    int prev = __shfl_up(j0, 1, WAVE);
+    if (lane == 0) prev = carry;
+    if (k < np)
+      for (int q = prev + 1; q <= j0; ++q) L.kf[q - j0f] = k;
+    carry = __builtin_amdgcn_readlane(j0, min(np - k0, WAVE) - 1);
   }
   if (lane == 0) L.kf[ncell] = np;
   wave_sync();
