@@ -440,10 +440,10 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   wave_sync();
 
   // (4) row projections: lanes over rows, the wave over every window column in
-  //     chunks of 8 columns; the loads of the next chunk are issued before the
-  //     current one is summed (two register buffers in turn).  The column address
-  //     is uniform (scalar) plus the lane's fixed row offset, and the padding
-  //     columns after the grid keep every prefetch in bounds.
+  //     chunks of CW columns (4 for the adjoint); the loads of the next chunk are
+  //     issued before the current one is summed (two register buffers in turn).
+  //     The column address is uniform (scalar) plus the lane's fixed row offset,
+  //     and the padding columns after the grid keep every prefetch in bounds.
   const int nrow = rhi - rlo + 1;
   if constexpr (MODE == VJP) {
     // the adjoint reads the difference surface, 4 columns per chunk (16 bytes per lane and column)
