@@ -59,7 +59,7 @@ template <int MODE> struct ModeInfo;
 // are in flight together); the adjoint reads 4-column chunks of the difference
 // surface.
 template <> struct ModeInfo<FWD> { static constexpr int NG = 1, NR = 1, NW = 2, GROUP = 8, CW = 4; typedef float V; };
-template <> struct ModeInfo<FIT> { static constexpr int NG = 2, NR = 3, NW = 8, GROUP = 8, CW = 8; typedef float2 V; };
+template <> struct ModeInfo<FIT> { static constexpr int NG = 2, NR = 3, NW = 8, GROUP = 8, CW = 4; typedef float2 V; };
 template <> struct ModeInfo<VJP> { static constexpr int NG = 4, NR = 4, NW = 2, GROUP = 4, CW = 4; typedef float4 V; };
 
 // Largest group over the modes (sizes the per-slot flags).
