@@ -408,12 +408,13 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def serve_leg(torch, saltbf, model, bands, seconds):
-    """Poisson arrivals at 2,000 req/s: submit each request at its arrival time, collect p50/p99."""
+def serve_leg(torch, saltbf, model, bands, seconds, **config):
+    """Poisson arrivals at 2,000 req/s: submit each request at its arrival time, collect p50/p99.
+    config: sb_config overrides for the serving context."""
     rate = 2000.0
     n_req = int(rate * (seconds + 0.5))
     reqs = synth.config4_requests(n_req, rate=rate)
-    ctx = saltbf.Context.from_model(model, bands)
+    ctx = saltbf.Context.from_model(model, bands, **config)
     dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     # true fluxes of every request in one batched forward call
     n_s = np.array([len(r.t) for r in reqs])

@@ -88,7 +88,7 @@ typedef struct {
   int32_t max_obs_per_fit;   /* observations per fit request (default 256, at most 1024) */
   int32_t max_slots;         /* fits resident on the device at once (default 1024) */
   int64_t hbm_budget_bytes;  /* device bytes the fit server may hold for requests (default 256 MiB) */
-  int32_t iters_per_tick;    /* LM iterations per server launch (default 10) */
+  int32_t iters_per_tick;    /* LM iterations per server launch (default 5) */
   int32_t fit_iters;         /* LM iterations per fit (default 50) */
   double lm_lambda0;         /* initial Marquardt damping (default 1e-3) */
   int64_t lds_limit_bytes;   /* LDS a workgroup may use; 0 (default): the device's per-workgroup maximum.

@@ -102,7 +102,7 @@ void sb_config_default(sb_config* cfg) {
   cfg->max_obs_per_fit = 256;
   cfg->max_slots = 1024;
   cfg->hbm_budget_bytes = 256ll << 20;
-  cfg->iters_per_tick = 10;
+  cfg->iters_per_tick = 5;
   cfg->fit_iters = 50;
   cfg->lm_lambda0 = 1e-3;
   cfg->lds_limit_bytes = 0;
