@@ -259,8 +259,9 @@ def main():
                     help="run one device copy of this size (for calibrating HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(supernovae shard with no exchange; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (supernovae, sweep "
+              "samples and fits are independent and would shard across GPUs with no exchange).",
+              file=sys.stderr)
         sys.exit(2)
     legs = set(x for x in args.legs.split(",") if x)
 

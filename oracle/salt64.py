@@ -14,8 +14,7 @@ Definitions (paper, section "Implementation"):
   the implementation paragraph states that the integral is taken with the
   trapezoidal rule along wavelength.
 
-Readings where the paper is silent or garbled (each is listed in the design
-notes of the repository):
+Readings where the paper is silent or garbled:
 
 * phase p = (t - t0)/(1+z) and the amplitude x0/(1+z) (the phase sentence of
   the model paragraph is garbled);
