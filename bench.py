@@ -267,7 +267,7 @@ def main():
 
     model = synth.make_model()
     bands = synth.make_bands(6)
-    truth = synth.config2()
+    truth = synth.batch_4096_sn()
     ev_params = synth.perturb(truth)
 
     cpu = None
@@ -321,7 +321,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "fwd+adjoint chi2 gradient, 4096 SN, uneven 20-200 obs, 6 bands (configs 2/3)",
+        "config": {"workload": "fwd+adjoint chi2 gradient, 4096 SN, uneven 20-200 obs, 6 bands",
                    "n_sn": truth.n_sn, "n_obs": n_obs, "bands": 6, "surface": "71x721", "parallelism": "none"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": profiled_traffic(PROFILE_VJP),
@@ -354,7 +354,7 @@ def main():
         log(f"fwd: {result['fwd']}")
 
     if "sweep" in legs:
-        sw = synth.config5a(n_samples=args.sweep_samples)
+        sw = synth.sweep_120_obs(n_samples=args.sweep_samples)
         smp = sw.samples
         no = len(sw.obs_t)
         f1 = ctx.bandflux(z=dv(np.float32([sw.theta_true[0]])), t0=dv(np.float32([sw.theta_true[1]])),
@@ -387,7 +387,7 @@ def main():
         log(f"sweep: {result['sweep']}")
 
     if "big" in legs:
-        big = synth.config5b()
+        big = synth.batch_65536_sn()
         Db = dev_batch(synth.perturb(big, k=7))
         fb = ctx.bandflux(**dev_batch(big)).cpu().numpy()
         bd, _, bw = synth.make_data(fb, big.sn_offsets, synth.noise_draws(big.n_obs, k=17))
@@ -414,7 +414,7 @@ def serve_leg(torch, saltbf, model, bands, seconds, **config):
     config: sb_config overrides for the serving context."""
     rate = 2000.0
     n_req = int(rate * (seconds + 0.5))
-    reqs = synth.config4_requests(n_req, rate=rate)
+    reqs = synth.fit_requests(n_req, rate=rate)
     ctx = saltbf.Context.from_model(model, bands, **config)
     dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     # true fluxes of every request in one batched forward call

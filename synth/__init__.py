@@ -9,7 +9,7 @@ here; quantities that need a model flux (noisy data, flux errors) are built
 by the caller from a flux it computed itself, through :func:`make_data`.
 
 All random numbers come from ``numpy.random.Generator(PCG64(SEED + k))``:
-k = 0 draws the model, k = 1..5 draw workload 1..5, larger k are free for
+k = 0 draws the model, k = 1..5 draw the five workloads below, larger k are free for
 tests.  Every floating value the GPU receives is first rounded to float32
 here, so both sides start from identical numbers.
 
@@ -214,7 +214,7 @@ def _sorted_obs(t, b):
     return t[order], b[order]
 
 
-def config1() -> Batch:
+def one_sn_40_obs() -> Batch:
     """1 supernova, 40 observations: 4 bands x 10 rest phases -15..45."""
     z, t0, x0, x1, c = 0.1, 0.0, 1e-5, 0.5, 0.05
     zf = float(np.float32(z))
@@ -255,7 +255,7 @@ def random_batch(k: int, n_sn: int, nobs_lo: int, nobs_hi: int, bands: List[Band
     return _finish(z, t0, x0, x1, c, ts, bs)
 
 
-def config2(n_sn: int = 4096, k: int = 2) -> Batch:
+def batch_4096_sn(n_sn: int = 4096, k: int = 2) -> Batch:
     """4,096 supernovae, n_s ~ U{20..200} observations, 6 bands, broad priors."""
     return random_batch(k, n_sn, 20, 200, make_bands(6), make_model())
 
@@ -308,7 +308,7 @@ class FitRequest:
     normals: np.ndarray
 
 
-def config4_requests(n_req: int, rate: float = 2000.0, k: int = 4, nobs_lo=8, nobs_hi=256) -> List[FitRequest]:
+def fit_requests(n_req: int, rate: float = 2000.0, k: int = 4, nobs_lo=8, nobs_hi=256) -> List[FitRequest]:
     """Poisson-arriving single-supernova fit requests with 8-256 observations in 2-6 bands."""
     g = rng(k)
     bands = make_bands(6)
@@ -343,7 +343,7 @@ class Sweep:
     samples: Batch          # n_sn = n_samples, no observations of its own (t, band empty)
 
 
-def config5a(n_samples: int = 1 << 20, k: int = 5) -> Sweep:
+def sweep_120_obs(n_samples: int = 1 << 20, k: int = 5) -> Sweep:
     """1 supernova with 120 observations in 6 bands, evaluated at many parameter samples."""
     g = rng(k)
     z, t0 = 0.1, 100.0
@@ -364,6 +364,6 @@ def config5a(n_samples: int = 1 << 20, k: int = 5) -> Sweep:
     return Sweep(f32(t), bb.astype(np.int32), f32r([z, t0, 1e-5, 0.5, 0.05]), smp)
 
 
-def config5b(n_sn: int = 65536, k: int = 6) -> Batch:
+def batch_65536_sn(n_sn: int = 65536, k: int = 6) -> Batch:
     """65,536 supernovae x 100 observations, broad priors."""
     return random_batch(k, n_sn, 100, 100, make_bands(6), make_model(), fixed_nobs=100)

@@ -47,8 +47,8 @@ def o6(model, bands6):
 
 
 @pytest.fixture(scope="module")
-def cfg2():
-    return synth.config2()
+def big_batch():
+    return synth.batch_4096_sn()
 
 
 def run_fwd(ctx, batch, torch):
@@ -71,25 +71,25 @@ def x0_per_obs(batch):
     return np.repeat(batch.x0.astype(np.float64), np.diff(batch.sn_offsets))
 
 
-# ----------------------------------------------------------------------------- workload 1
+# ----------------------------------------------------------------------------- one supernova, 40 observations
 
-def test_cfg1_forward_all_40(ctx4, o4, torch):
-    b = synth.config1()
-    print("case: config1 forward, 40 obs", flush=True)
+def test_one_sn_forward_all_40(ctx4, o4, torch):
+    b = synth.one_sn_40_obs()
+    print("case: one_sn_40_obs forward, 40 obs", flush=True)
     f = run_fwd(ctx4, b, torch)
     f64 = o4.bandflux(b)
     err = flux_rel_err(f, f64, b.sn_offsets)
-    print(f"cfg1 flux rel err max {err.max():.3e} median {np.median(err):.3e}")
+    print(f"one SN flux rel err max {err.max():.3e} median {np.median(err):.3e}")
     assert err.max() <= FLUX_TOL
 
 
-def test_cfg1_jacobian_rows(ctx4, o4, torch):
-    b = synth.config1()
+def test_one_sn_jacobian_rows(ctx4, o4, torch):
+    b = synth.one_sn_40_obs()
     f, J, _ = run_jac(ctx4, b, torch)
     f64, J64 = o4.jac(b)
     assert flux_rel_err(f, f64, b.sn_offsets).max() <= FLUX_TOL
     err = jac_rel_err(J, J64, x0_per_obs(b), b.sn_offsets)
-    print(f"cfg1 jacobian rel err max per param {err.max(axis=0)}")
+    print(f"one SN jacobian rel err max per param {err.max(axis=0)}")
     assert err.max() <= GRAD_TOL
 
 
@@ -120,7 +120,7 @@ def test_small_batch_every_result(ctx6, o6, torch):
     assert flux_rel_err(f_fwd, f64, b.sn_offsets).max() <= FLUX_TOL
 
 
-# ----------------------------------------------------------------------------- workloads 2 and 3
+# ----------------------------------------------------------------------------- the 4,096-supernova batch
 
 def sample_sns(batch, n=40, seed=3):
     n_s = np.diff(batch.sn_offsets)
@@ -131,25 +131,25 @@ def sample_sns(batch, n=40, seed=3):
     return np.array(sorted(pick))
 
 
-def test_cfg2_forward_full_size_sampled(ctx6, o6, cfg2, torch):
-    print(f"case: config2 forward, {cfg2.n_sn} SN, {cfg2.n_obs} obs", flush=True)
-    f = run_fwd(ctx6, cfg2, torch)
+def test_batch_4096_forward_sampled(ctx6, o6, big_batch, torch):
+    print(f"case: batch_4096_sn forward, {big_batch.n_sn} SN, {big_batch.n_obs} obs", flush=True)
+    f = run_fwd(ctx6, big_batch, torch)
     assert np.all(np.isfinite(f))
-    idx = sample_sns(cfg2)
-    sub = cfg2.subset(idx)
+    idx = sample_sns(big_batch)
+    sub = big_batch.subset(idx)
     f64 = o6.bandflux(sub)
-    sel = np.concatenate([np.arange(cfg2.sn_offsets[s], cfg2.sn_offsets[s + 1]) for s in idx])
+    sel = np.concatenate([np.arange(big_batch.sn_offsets[s], big_batch.sn_offsets[s + 1]) for s in idx])
     err = flux_rel_err(f[sel], f64, sub.sn_offsets)
-    print(f"cfg2 sampled {len(idx)} SN / {len(sel)} obs: flux rel err max {err.max():.3e} "
+    print(f"big_batch sampled {len(idx)} SN / {len(sel)} obs: flux rel err max {err.max():.3e} "
           f"p99 {np.percentile(err, 99):.3e} median {np.median(err):.3e}")
     assert err.max() <= FLUX_TOL
 
 
-def test_cfg3_chi2_gradient_full_size_sampled(ctx6, o6, cfg2, torch):
-    """Workload 3: chi-square gradient at perturbed parameters, full batch on the GPU,
+def test_batch_4096_chi2_gradient_sampled(ctx6, o6, big_batch, torch):
+    """Chi-square gradient of the 4,096-supernova batch at perturbed parameters, full batch on the GPU,
     sampled supernovae against the oracle's analytic FP64 gradient."""
-    print("case: config3 chi2 gradient", flush=True)
-    truth = cfg2
+    print("case: 4096-SN chi2 gradient", flush=True)
+    truth = big_batch
     ev = synth.perturb(truth)
     idx = sample_sns(truth, n=32, seed=5)
     sub_true = truth.subset(idx)
@@ -173,16 +173,16 @@ def test_cfg3_chi2_gradient_full_size_sampled(ctx6, o6, cfg2, torch):
     ec = np.abs(chi2 - c64) / np.abs(c64)
     ef = flux_rel_err(r["flux"].cpu().numpy()[sel], f64, sub_ev.sn_offsets)
     en = grad_norm_err(grad, g64, sub_ev.x0)
-    print(f"cfg3: grad rel err max {eg.max():.3e} (per param {eg.max(axis=0)}), norm-wise {en.max():.3e}, "
+    print(f"4096-SN chi2 gradient: grad rel err max {eg.max():.3e} (per param {eg.max(axis=0)}), norm-wise {en.max():.3e}, "
           f"chi2 {ec.max():.3e}, flux {ef.max():.3e}")
     assert eg.max() <= GRAD_TOL
     assert ec.max() <= 1e-4
     assert ef.max() <= FLUX_TOL
 
 
-def test_run_twice_bitwise(ctx6, cfg2, torch):
-    d = to_dev(cfg2, torch)
-    cot = torch.ones(cfg2.n_obs, dtype=torch.float32, device="cuda")
+def test_run_twice_bitwise(ctx6, big_batch, torch):
+    d = to_dev(big_batch, torch)
+    cot = torch.ones(big_batch.n_obs, dtype=torch.float32, device="cuda")
     a = ctx6.bandflux_vjp(**d, cotangent=cot, want_flux=True)
     b = ctx6.bandflux_vjp(**d, cotangent=cot, want_flux=True)
     torch.cuda.synchronize()
@@ -194,11 +194,11 @@ def test_run_twice_bitwise(ctx6, cfg2, torch):
     assert rel < 1e-6
 
 
-def test_prepared_calls_match_plain_calls(ctx6, cfg2, torch):
+def test_prepared_calls_match_plain_calls(ctx6, big_batch, torch):
     """A prepared call launches the same kernel on the same buffers: bitwise equal to the plain call,
     also after the parameter buffers are updated in place between launches."""
-    d = to_dev(cfg2, torch)
-    cot = torch.ones(cfg2.n_obs, dtype=torch.float32, device="cuda")
+    d = to_dev(big_batch, torch)
+    cot = torch.ones(big_batch.n_obs, dtype=torch.float32, device="cuda")
     pv = ctx6.prepare_bandflux_vjp(**d, cotangent=cot, want_flux=True)
     pf = ctx6.prepare_bandflux(**d)
     for step in range(2):
@@ -213,13 +213,13 @@ def test_prepared_calls_match_plain_calls(ctx6, cfg2, torch):
     ctx6.device_check()
 
 
-def test_single_wave_workgroups_when_lds_is_short(sb, model, bands6, cfg2, torch):
+def test_single_wave_workgroups_when_lds_is_short(sb, model, bands6, big_batch, torch):
     """With a 12 KiB LDS limit every kernel runs one wave per workgroup instead of several: the
     per-observation results are bitwise those of the multi-wave kernels (each band's projections are
     built by one wave either way) and the per-supernova gradient differs only by reduction order."""
     small = sb.Context.from_model(model, bands6, lds_limit_bytes=12 * 1024)
     full = sb.Context.from_model(model, bands6)
-    ev = synth.perturb(cfg2)
+    ev = synth.perturb(big_batch)
     d = to_dev(ev, torch)
     cot = torch.from_numpy(np.random.default_rng(11).normal(size=ev.n_obs).astype(np.float32)).cuda()
     a = small.bandflux_vjp(**d, cotangent=cot, want_flux=True)
@@ -260,11 +260,11 @@ def test_many_bands_and_a_long_light_curve(sb, model, torch):
     ctx.close()
 
 
-def test_results_do_not_depend_on_the_rest_of_the_batch(ctx6, cfg2, torch):
+def test_results_do_not_depend_on_the_rest_of_the_batch(ctx6, big_batch, torch):
     """Every supernova's flux, gradient and chi-square are bitwise the same whether it is evaluated
     in the full 4,096-supernova batch or in a chunk of 1,000 (other neighbours, other workgroup
     indices, a differently filled device)."""
-    ev = synth.perturb(cfg2)
+    ev = synth.perturb(big_batch)
     g = np.random.default_rng(21)
     data = g.normal(size=ev.n_obs).astype(np.float32)
     w = np.abs(g.normal(size=ev.n_obs)).astype(np.float32)
@@ -433,7 +433,7 @@ def test_blueshifted_window_capacity(ctx6, o6, torch, sb):
 
 def test_host_argument_errors(ctx6, torch, sb):
     import ctypes
-    b = synth.config1()
+    b = synth.one_sn_40_obs()
     d = to_dev(b, torch)
     with pytest.raises(TypeError):
         ctx6.bandflux(**{**d, "t": d["t"].cpu()})
@@ -450,12 +450,12 @@ def test_host_argument_errors(ctx6, torch, sb):
     assert len(L.sb_last_error()) > 0
 
 
-# ----------------------------------------------------------------------------- sweep (workload 5)
+# ----------------------------------------------------------------------------- sweep (one observation table, many samples)
 
 def test_sweep_matches_plain_kernel_and_oracle(ctx6, o6, torch):
     """Broadcast sweep == per-supernova kernel on the materialised batch (bitwise),
     and both match the oracle on sampled parameter sets."""
-    sw = synth.config5a(n_samples=4096)
+    sw = synth.sweep_120_obs(n_samples=4096)
     smp = sw.samples
     n_obs = len(sw.obs_t)
     f_true = o6.bandflux(synth.Batch(np.float32([sw.theta_true[0]]), np.float32([sw.theta_true[1]]),

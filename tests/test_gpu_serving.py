@@ -34,7 +34,7 @@ def o6(model, bands6):
 @pytest.fixture(scope="module")
 def requests(o6):
     """Workload-4 requests with noisy data built from the oracle's true fluxes."""
-    reqs = synth.config4_requests(40, k=44)
+    reqs = synth.fit_requests(40, k=44)
     out = []
     for r in reqs:
         b = single_batch(r)

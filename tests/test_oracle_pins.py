@@ -165,7 +165,7 @@ def o4(model, bands4):
 
 
 def test_p4_linear_in_x0_affine_in_x1(o4):
-    b = synth.config1()
+    b = synth.one_sn_40_obs()
     f = o4.bandflux(b)
     f2 = o4.bandflux(b.with_params(x0=b.x0 * 2))
     np.testing.assert_allclose(f2, 2 * f, rtol=1e-14)
@@ -180,7 +180,7 @@ def test_p4_linear_in_x0_affine_in_x1(o4):
 
 def test_p5_c_zero_reduction(model, bands4):
     """At c = 0 the colour law drops out: same flux for any colour-law coefficients."""
-    b = synth.config1().with_params(c=[0.0])
+    b = synth.one_sn_40_obs().with_params(c=[0.0])
     o1 = oracle.Oracle(model, bands4)
     other = synth.Model(m0=model.m0, m1=model.m1, cl_coef=np.array([3.0, -1.0, 0.5]))
     o2 = oracle.Oracle(other, bands4)
@@ -195,7 +195,7 @@ def test_p5_c_zero_reduction(model, bands4):
 
 def test_p6_time_shift_and_z0(o4):
     """f depends on t - t0 only; at z = 0 the amplitude is x0 and phases are t - t0."""
-    b = synth.config1()
+    b = synth.one_sn_40_obs()
     f = o4.bandflux(b)
     # shift in float64 so that t - t0 stays exact
     sh = synth.Batch(b.z, b.t0, b.x0, b.x1, b.c, b.t.astype(np.float64) + 64.25, b.band, b.sn_offsets)
@@ -326,7 +326,7 @@ def test_p8_quadrature_converges_to_quad(model):
 def test_p9_gradient_vs_central_differences(model, bands6):
     """Analytic d f/d(z, t0, x0, x1, c) against FP64 central differences."""
     o = oracle.Oracle(model, bands6)
-    b = synth.config2(n_sn=6)
+    b = synth.batch_4096_sn(n_sn=6)
     P = b.params().astype(np.float64)
     f, J = o.jac(b, P)
     scale = np.array([0.1, 1.0, 1.0, 1.0, 0.1])
@@ -344,7 +344,7 @@ def test_p9_gradient_vs_central_differences(model, bands6):
 
 def test_vjp_and_chi2_gradient(model, bands6):
     o = oracle.Oracle(model, bands6)
-    b = synth.config2(n_sn=5)
+    b = synth.batch_4096_sn(n_sn=5)
     g = np.random.default_rng(5)
     cot = g.normal(size=b.n_obs)
     f, J = o.jac(b)
@@ -372,7 +372,7 @@ def test_p11_fit_recovers_truth(model, bands6):
     """LM fit of noise-free data recovers the true parameters with chi2 -> 0."""
     o = oracle.Oracle(model, bands6)
     fo = oracle.FitOracle(o)
-    reqs = synth.config4_requests(3, k=41)
+    reqs = synth.fit_requests(3, k=41)
     for r in reqs:
         b = synth.Batch(np.float32([r.z]), np.float32([r.theta_true[0]]), np.float32([r.theta_true[1]]),
                         np.float32([r.theta_true[2]]), np.float32([r.theta_true[3]]), r.t, r.band,
@@ -425,3 +425,18 @@ def test_p11_lm_iterates_on_linear_least_squares():
     # the first step differs from the undamped Gauss-Newton step by the damping term
     gn = q0 + np.linalg.solve(H, X.T @ (w * (d - X @ q0)))
     assert np.max(np.abs(seq[0] - gn)) > 1e-6
+
+
+def test_tiny_exact_fixture_is_its_own_exact_derivation():
+    """The stored P10 value equals an exact rational re-derivation (no oracle, no GPU involved)."""
+    import importlib.util
+    import json
+    from fractions import Fraction
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tiny_exact_derivation.py")
+    spec = importlib.util.spec_from_file_location("tiny_exact_derivation", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    with open(mod.PATH) as fh:
+        fx = json.load(fh)
+    stored = Fraction(fx["expected_flux_times_hc"]["num"], fx["expected_flux_times_hc"]["den"])
+    assert mod.derive(fx) == stored

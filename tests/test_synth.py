@@ -5,8 +5,8 @@ import synth
 
 
 def test_deterministic_and_shapes():
-    a = synth.config2(n_sn=50)
-    b = synth.config2(n_sn=50)
+    a = synth.batch_4096_sn(n_sn=50)
+    b = synth.batch_4096_sn(n_sn=50)
     assert np.array_equal(a.t, b.t) and np.array_equal(a.band, b.band) and np.array_equal(a.z, b.z)
     assert a.sn_offsets[0] == 0 and a.sn_offsets[-1] == a.n_obs
     n = np.diff(a.sn_offsets)
@@ -16,8 +16,8 @@ def test_deterministic_and_shapes():
     assert a.band.dtype == np.int32 and a.sn_offsets.dtype == np.int32
 
 
-def test_config2_size_and_eligibility(model, bands6):
-    b = synth.config2()
+def test_batch_4096_size_and_eligibility(model, bands6):
+    b = synth.batch_4096_sn()
     assert b.n_sn == 4096 and 400_000 < b.n_obs < 500_000
     # every observation's band keeps its rest window inside the surface grid
     for s in range(0, b.n_sn, 97):
@@ -28,10 +28,10 @@ def test_config2_size_and_eligibility(model, bands6):
         assert np.all(np.diff(b.band[lo:hi]) >= 0)
 
 
-def test_config1_and_sweep():
-    c1 = synth.config1()
+def test_one_sn_and_sweep():
+    c1 = synth.one_sn_40_obs()
     assert c1.n_sn == 1 and c1.n_obs == 40 and set(c1.band) == {0, 1, 2, 3}
-    sw = synth.config5a(n_samples=1000)
+    sw = synth.sweep_120_obs(n_samples=1000)
     assert len(sw.obs_t) == 120 and sw.samples.n_sn == 1000
     assert sw.samples.z.max() < 0.75
 
