@@ -82,6 +82,13 @@ typedef struct {
   double cl_wave_b, cl_wave_v;
 } sb_model_desc;
 
+/* Band quadrature rules on the grid of N equal intervals of width Delta <= max_spacing
+ * between a band's first and last sample wavelengths.  Trapezoid (the bandflux
+ * integral as the paper evaluates it, section "Implementation"): the N + 1
+ * interval ends, weights Delta/2 at both ends and Delta inside.  Midpoint: the N
+ * interval midpoints, weight Delta each. */
+enum { SB_QUAD_TRAPEZOID = 0, SB_QUAD_MIDPOINT = 1 };
+
 /* Library configuration; fill with sb_config_default() and override. */
 typedef struct {
   double max_spacing;        /* quadrature spacing bound in Angstrom (default 5) */
@@ -91,6 +98,8 @@ typedef struct {
   int32_t iters_per_tick;    /* LM iterations per server launch (default 5) */
   int32_t fit_iters;         /* LM iterations per fit (default 50) */
   double lm_lambda0;         /* initial Marquardt damping (default 1e-3) */
+  int32_t quad_rule;         /* band quadrature: SB_QUAD_TRAPEZOID (default, the paper's rule) or
+                                SB_QUAD_MIDPOINT */
   int64_t lds_limit_bytes;   /* LDS a workgroup may use; 0 (default): the device's per-workgroup maximum.
                                 Kernels run several waves per workgroup where that fits, else one;
                                 bands whose one-wave form does not fit are refused by sb_add_band. */
@@ -110,16 +119,17 @@ sb_status sb_destroy(sb_ctx *ctx);
 
 /* Register a bandpass (the paper's bandpass registration): n >= 2 samples of
  * (wave [Angstrom, strictly increasing], trans >= 0), host arrays, copied.
- * Builds its trapezoid grid (at most SB_MAX_BAND_POINTS nodes) and stores
+ * Builds its quadrature grid (cfg.quad_rule, at most SB_MAX_BAND_POINTS nodes) and stores
  * lam_k and W_k = w_k lam_k T(lam_k)/(h c) in float32 on the device.
  * Synchronous.  Not allowed while compute calls of this context are in
  * flight.  *band_id receives 0, 1, 2, ... in registration order. */
 sb_status sb_add_band(sb_ctx *ctx, const double *wave, const double *trans, int32_t n, int32_t *band_id);
 
-/* Host-only helper (no context, no GPU): the quadrature grid sb_add_band builds.
- * Writes at most cap nodes to lam_out/weight_out (float32, weight = W_k above);
- * *n_points receives the node count.  SB_ERR_ARG if it exceeds cap. */
-sb_status sb_band_grid(const double *wave, const double *trans, int32_t n, double max_spacing,
+/* Host-only helper (no context, no GPU): the quadrature grid sb_add_band builds
+ * with rule (SB_QUAD_TRAPEZOID or SB_QUAD_MIDPOINT).  Writes at most cap nodes to
+ * lam_out/weight_out (float32, weight = W_k above); *n_points receives the node
+ * count.  SB_ERR_ARG if it exceeds cap. */
+sb_status sb_band_grid(const double *wave, const double *trans, int32_t n, double max_spacing, int32_t rule,
                        int32_t cap, float *lam_out, float *weight_out, int32_t *n_points);
 
 /* Batch flags. */

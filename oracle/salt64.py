@@ -42,23 +42,31 @@ PARAM_NAMES = ("z", "t0", "x0", "x1", "c")
 
 # ----------------------------------------------------------------------------- band grid
 
-def band_grid(wave, trans, spacing=5.0):
-    """Trapezoid quadrature grid of one band: nodes lam_k, transmission T_k, weights w_k.
+def band_grid(wave, trans, spacing=5.0, rule="trapezoid"):
+    """Quadrature grid of one band: nodes lam_k, transmission T_k, weights w_k.
 
-    N = ceil((U - L)/spacing) equal intervals between the first (L) and last (U)
-    tabulated wavelengths; T is linearly interpolated from the samples; the
-    trapezoid weights are Delta/2 at both ends and Delta inside.
+    N = ceil((U - L)/spacing) equal intervals of width Delta between the first (L)
+    and last (U) tabulated wavelengths; T is linearly interpolated from the samples.
+    rule "trapezoid" (the paper's rule, section "Implementation"): the N + 1 interval
+    ends, weights Delta/2 at both ends and Delta inside.  rule "midpoint": the N
+    interval midpoints, weight Delta each.
     """
     wave = np.asarray(wave, dtype=np.float64)
     trans = np.asarray(trans, dtype=np.float64)
     L, U = wave[0], wave[-1]
     n = max(1, int(np.ceil((U - L) / spacing - 1e-9)))
     delta = (U - L) / n
-    lam = L + delta * np.arange(n + 1)
-    lam[-1] = U
+    if rule == "trapezoid":
+        lam = L + delta * np.arange(n + 1)
+        lam[-1] = U
+        w = np.full(n + 1, delta)
+        w[0] = w[-1] = 0.5 * delta
+    elif rule == "midpoint":
+        lam = L + delta * (np.arange(n) + 0.5)
+        w = np.full(n, delta)
+    else:
+        raise ValueError(f"unknown quadrature rule {rule!r}")
     T = np.interp(lam, wave, trans)
-    w = np.full(n + 1, delta)
-    w[0] = w[-1] = 0.5 * delta
     return lam, T, w
 
 
@@ -145,11 +153,11 @@ def colour_law(model, mu, deriv=False):
 class Oracle:
     """Model surfaces (float32 nodes held in float64) and band grids, evaluated in FP64."""
 
-    def __init__(self, model, bands, spacing=5.0):
+    def __init__(self, model, bands, spacing=5.0, rule="trapezoid"):
         self.model = model
         self.m0 = np.asarray(model.m0, dtype=np.float64)
         self.m1 = np.asarray(model.m1, dtype=np.float64)
-        self.grids = [band_grid(b.wave, b.trans, spacing) for b in bands]
+        self.grids = [band_grid(b.wave, b.trans, spacing, rule) for b in bands]
 
     def _group(self, b, z, t0, x0, x1, c, t, jac):
         """Flux (and five partials) of the observations t of one supernova in band b."""

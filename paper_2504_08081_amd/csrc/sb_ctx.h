@@ -15,8 +15,8 @@ class Server;
 sb_status set_error(sb_status st, const std::string& msg);
 double now_seconds();
 
-// Quadrature grid of one band, float64: nodes, and W_k = w_k lam_k T_k / (hc).
-sb_status build_band_grid(const double* wave, const double* trans, int n, double spacing,
+// Quadrature grid of one band (trapezoid or midpoint rule), float64: nodes, and W_k = w_k lam_k T_k / (hc).
+sb_status build_band_grid(const double* wave, const double* trans, int n, double spacing, int rule,
                           std::vector<double>& lam, std::vector<double>& W);
 
 }  // namespace sbh

@@ -38,10 +38,11 @@ double now_seconds() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-sb_status build_band_grid(const double* wave, const double* trans, int n, double spacing,
+sb_status build_band_grid(const double* wave, const double* trans, int n, double spacing, int rule,
                           std::vector<double>& lam, std::vector<double>& W) {
   if (!wave || !trans || n < 2) return set_error(SB_ERR_ARG, "band: need at least 2 samples");
   if (!(spacing > 0.0) || !std::isfinite(spacing)) return set_error(SB_ERR_ARG, "band: spacing must be > 0");
+  if (rule != SB_QUAD_TRAPEZOID && rule != SB_QUAD_MIDPOINT) return set_error(SB_ERR_ARG, "band: unknown rule");
   if (!finite_all(wave, n) || !finite_all(trans, n)) return set_error(SB_ERR_ARG, "band: non-finite sample");
   for (int i = 0; i < n; ++i) {
     if (i > 0 && !(wave[i] > wave[i - 1])) return set_error(SB_ERR_ARG, "band: wavelengths must increase");
@@ -55,16 +56,20 @@ sb_status build_band_grid(const double* wave, const double* trans, int n, double
   if (N < 1) N = 1;
   if (N + 1 > SB_MAX_BAND_POINTS) return set_error(SB_ERR_ARG, "band: more than SB_MAX_BAND_POINTS nodes");
   const double delta = (U - L) / (double)N;
-  lam.assign(N + 1, 0.0);
-  W.assign(N + 1, 0.0);
+  // trapezoid: the N + 1 interval ends, weights Delta/2 at the ends and Delta inside;
+  // midpoint: the N interval midpoints, weight Delta
+  const bool mid = rule == SB_QUAD_MIDPOINT;
+  const long n_nodes = mid ? N : N + 1;
+  lam.assign(n_nodes, 0.0);
+  W.assign(n_nodes, 0.0);
   int seg = 0;
-  for (long k = 0; k <= N; ++k) {
-    const double x = (k == N) ? U : L + delta * (double)k;
+  for (long k = 0; k < n_nodes; ++k) {
+    const double x = mid ? L + delta * ((double)k + 0.5) : ((k == N) ? U : L + delta * (double)k);
     while (seg < n - 2 && x > wave[seg + 1]) ++seg;
     // linear interpolation of the transmission between samples seg and seg+1
     const double slope = (trans[seg + 1] - trans[seg]) / (wave[seg + 1] - wave[seg]);
     const double T = slope * (x - wave[seg]) + trans[seg];
-    const double w = (k == 0 || k == N) ? 0.5 * delta : delta;
+    const double w = (!mid && (k == 0 || k == N)) ? 0.5 * delta : delta;
     lam[k] = x;
     W[k] = w * x * T / HC_ERG_ANGSTROM;
   }
@@ -105,14 +110,16 @@ void sb_config_default(sb_config* cfg) {
   cfg->iters_per_tick = 5;
   cfg->fit_iters = 50;
   cfg->lm_lambda0 = 1e-3;
+  cfg->quad_rule = SB_QUAD_TRAPEZOID;
   cfg->lds_limit_bytes = 0;
 }
 
-sb_status sb_band_grid(const double* wave, const double* trans, int32_t n, double max_spacing, int32_t cap,
+sb_status sb_band_grid(const double* wave, const double* trans, int32_t n, double max_spacing, int32_t rule,
+                       int32_t cap,
                        float* lam_out, float* weight_out, int32_t* n_points) {
   if (!n_points) return set_error(SB_ERR_ARG, "sb_band_grid: n_points is NULL");
   std::vector<double> lam, W;
-  sb_status st = sbh::build_band_grid(wave, trans, n, max_spacing, lam, W);
+  sb_status st = sbh::build_band_grid(wave, trans, n, max_spacing, rule, lam, W);
   if (st != SB_OK) return st;
   *n_points = (int32_t)lam.size();
   if ((int)lam.size() > cap) return set_error(SB_ERR_ARG, "sb_band_grid: cap too small");
@@ -158,7 +165,8 @@ sb_status sb_create(const sb_model_desc* md, const sb_config* cfg_in, int device
   if (cfg_in) cfg = *cfg_in;
   if (!(cfg.max_spacing > 0) || cfg.max_obs_per_fit < 1 || cfg.max_obs_per_fit > 1024 || cfg.max_slots < 1 ||
       cfg.max_slots > 65536 || cfg.hbm_budget_bytes < 0 || cfg.iters_per_tick < 1 || cfg.fit_iters < 0 ||
-      !(cfg.lm_lambda0 > 0) || cfg.lds_limit_bytes < 0)
+      !(cfg.lm_lambda0 > 0) || cfg.lds_limit_bytes < 0 ||
+      (cfg.quad_rule != SB_QUAD_TRAPEZOID && cfg.quad_rule != SB_QUAD_MIDPOINT))
     return set_error(SB_ERR_ARG, "sb_create: bad configuration");
 
   hipError_t e = hipSetDevice(device);
@@ -258,7 +266,7 @@ sb_status sb_add_band(sb_ctx* ctx, const double* wave, const double* trans, int3
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (ctx->n_bands >= SB_MAX_BANDS) return set_error(SB_ERR_ARG, "sb_add_band: registry full");
   std::vector<double> lam, W;
-  sb_status st = sbh::build_band_grid(wave, trans, n, ctx->cfg.max_spacing, lam, W);
+  sb_status st = sbh::build_band_grid(wave, trans, n, ctx->cfg.max_spacing, ctx->cfg.quad_rule, lam, W);
   if (st != SB_OK) return st;
   const int np = (int)lam.size();
   // surface window of the band for rest wavelengths lam/(1+z), z >= WINDOW_Z_MIN: at most

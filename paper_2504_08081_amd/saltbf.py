@@ -20,6 +20,7 @@ SB_OK, SB_PENDING, SB_CANCELLED, SB_FIT_DIVERGED = 0, 1, 2, 3
 SB_ERR_ARG, SB_ERR_RANGE, SB_ERR_DEVICE, SB_ERR_NOMEM = -1, -2, -3, -4
 SB_ERR_BUDGET, SB_ERR_STATE, SB_ERR_NOTFOUND = -5, -6, -7
 SB_OBS_BROADCAST, SB_OUT_CHI2 = 1, 2
+SB_QUAD_TRAPEZOID, SB_QUAD_MIDPOINT = 0, 1
 SB_MAX_BANDS, SB_MAX_BAND_POINTS, SB_N_PARAMS = 64, 2048, 5
 
 EXPORTED = (
@@ -46,7 +47,8 @@ class Config(ctypes.Structure):
     _fields_ = [("max_spacing", ctypes.c_double), ("max_obs_per_fit", ctypes.c_int32),
                 ("max_slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64),
                 ("iters_per_tick", ctypes.c_int32), ("fit_iters", ctypes.c_int32),
-                ("lm_lambda0", ctypes.c_double), ("lds_limit_bytes", ctypes.c_int64)]
+                ("lm_lambda0", ctypes.c_double), ("quad_rule", ctypes.c_int32),
+                ("lds_limit_bytes", ctypes.c_int64)]
 
 
 class Batch(ctypes.Structure):
@@ -113,7 +115,8 @@ def lib():
         L.sb_destroy.restype = st
         L.sb_add_band.argtypes = [vp, _f64p, _f64p, ctypes.c_int32, _i32p]
         L.sb_add_band.restype = st
-        L.sb_band_grid.argtypes = [_f64p, _f64p, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _f32p, _f32p, _i32p]
+        L.sb_band_grid.argtypes = [_f64p, _f64p, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                   _f32p, _f32p, _i32p]
         L.sb_band_grid.restype = st
         L.sb_bandflux.argtypes = [vp, ctypes.POINTER(Batch), vp, vp]
         L.sb_bandflux.restype = st
@@ -154,15 +157,16 @@ def default_config(**over) -> Config:
     return cfg
 
 
-def band_grid(wave, trans, max_spacing=5.0):
-    """Host-only quadrature grid of a band as the library builds it: (lam_k, W_k) float32."""
+def band_grid(wave, trans, max_spacing=5.0, rule=0):
+    """Host-only quadrature grid of a band as the library builds it: (lam_k, W_k) float32.
+    rule: SB_QUAD_TRAPEZOID (0) or SB_QUAD_MIDPOINT (1)."""
     w = np.ascontiguousarray(wave, np.float64)
     t = np.ascontiguousarray(trans, np.float64)
     lam = np.zeros(SB_MAX_BAND_POINTS, np.float32)
     W = np.zeros(SB_MAX_BAND_POINTS, np.float32)
     n = ctypes.c_int32(0)
     _check(lib().sb_band_grid(w.ctypes.data_as(_f64p), t.ctypes.data_as(_f64p), len(w), float(max_spacing),
-                              SB_MAX_BAND_POINTS, lam.ctypes.data_as(_f32p), W.ctypes.data_as(_f32p),
+                              int(rule), SB_MAX_BAND_POINTS, lam.ctypes.data_as(_f32p), W.ctypes.data_as(_f32p),
                               ctypes.byref(n)), "sb_band_grid")
     return lam[: n.value].copy(), W[: n.value].copy()
 

@@ -44,14 +44,17 @@ def test_status_strings():
         assert len(L.sb_status_string(st)) > 0
     cfg = sb.default_config()
     assert cfg.max_spacing == 5.0 and cfg.fit_iters == 50 and cfg.max_obs_per_fit == 256
+    assert cfg.quad_rule == sb.SB_QUAD_TRAPEZOID
 
 
+@pytest.mark.parametrize("rule", ["trapezoid", "midpoint"])
 @pytest.mark.parametrize("nb,idx", [(4, 0), (6, 2), (6, 5)])
-def test_band_grid_matches_oracle(nb, idx):
+def test_band_grid_matches_oracle(nb, idx, rule):
     sb = _lib()
     b = synth.make_bands(nb)[idx]
-    lam, W = sb.band_grid(b.wave, b.trans, 5.0)
-    lam64, T64, w64 = oracle.band_grid(b.wave, b.trans, 5.0)
+    code = {"trapezoid": sb.SB_QUAD_TRAPEZOID, "midpoint": sb.SB_QUAD_MIDPOINT}[rule]
+    lam, W = sb.band_grid(b.wave, b.trans, 5.0, rule=code)
+    lam64, T64, w64 = oracle.band_grid(b.wave, b.trans, 5.0, rule=rule)
     assert len(lam) == len(lam64)
     assert np.array_equal(lam, lam64.astype(np.float32))
     W64 = w64 * lam64 * T64 / oracle.HC
@@ -67,8 +70,12 @@ def test_band_grid_errors():
         sb.band_grid([1.0, 2.0], [1.0, -1.0])
     with pytest.raises(sb.SaltBFError):
         sb.band_grid([0.0, 20000.0], [1.0, 1.0])   # more nodes than SB_MAX_BAND_POINTS
+    with pytest.raises(sb.SaltBFError):
+        sb.band_grid([3.0, 5.0, 7.0], [0.5, 1.0, 0.25], 1.0, rule=2)
     lam, W = sb.band_grid([3.0, 5.0, 7.0], [0.5, 1.0, 0.25], 1.0)
     np.testing.assert_array_equal(lam, np.float32([3, 4, 5, 6, 7]))
+    lam, W = sb.band_grid([3.0, 5.0, 7.0], [0.5, 1.0, 0.25], 1.0, rule=sb.SB_QUAD_MIDPOINT)
+    np.testing.assert_array_equal(lam, np.float32([3.5, 4.5, 5.5, 6.5]))
 
 
 def test_binding_structs_match_the_c_header(tmp_path):

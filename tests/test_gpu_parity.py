@@ -352,6 +352,47 @@ def test_flat_spectrum_tophat_gpu(sb, torch, z):
     ctx.close()
 
 
+def test_midpoint_rule_context(sb, torch, model, bands6):
+    """A context built with the midpoint quadrature rule against the oracle on the same rule:
+    every flux, Jacobian row and gradient of a 64-supernova batch; and, on a flat spectrum with
+    a top-hat band (linear integrand, where the midpoint rule is exact), the closed form."""
+    ctx = sb.Context.from_model(model, bands6, quad_rule=sb.SB_QUAD_MIDPOINT)
+    om = oracle.Oracle(model, bands6, rule="midpoint")
+    b = synth.random_batch(43, 64, 1, 200, bands6, model)
+    g = np.random.default_rng(11)
+    cot = g.normal(size=b.n_obs).astype(np.float32)
+    f, J, grad = run_jac(ctx, b, torch, cot)
+    f64, J64 = om.jac(b)
+    g64 = oracle.segment_sum(cot.astype(np.float64)[:, None] * J64, b.sn_offsets)
+    ef = flux_rel_err(f, f64, b.sn_offsets)
+    ej = jac_rel_err(J, J64, x0_per_obs(b), b.sn_offsets)
+    en = grad_norm_err(grad, g64, b.x0)
+    print(f"midpoint rule: flux {ef.max():.3e} jac {ej.max():.3e} grad norm-wise {en.max():.3e}")
+    assert ef.max() <= FLUX_TOL and ej.max() <= GRAD_TOL and en.max() <= GRAD_TOL
+    # the two rules differ by the quadrature error, far above FP32 rounding
+    ft = oracle.Oracle(model, bands6).bandflux(b)
+    assert np.max(np.abs(ft - f64) / np.abs(f64).max()) > 1e-5
+    ctx.close()
+
+    K = 0.75
+    m0 = np.full((71, 721), K, np.float32)
+    ctx = sb.Context(m0, np.zeros_like(m0), -20.0, 1.0, 2000.0, 10.0, [-0.9, 0.1, 0.01], 4302.57, 5428.55,
+                     quad_rule=sb.SB_QUAD_MIDPOINT)
+    a, bnd = 4000.0, 5230.0
+    tb = synth.tophat_band(a, bnd)
+    ctx.add_band(tb.wave, tb.trans)
+    z = 0.4
+    t = np.float32([3.0, 17.25, -9.5, 40.0])
+    tb1 = synth.Batch(np.float32([z]), np.float32([1.0]), np.float32([3e-5]), np.float32([0.0]), np.float32([0.0]),
+                      t, np.zeros(4, np.int32), np.int32([0, 4]))
+    f, J, _ = run_jac(ctx, tb1, torch)
+    zf, x0f = float(np.float32(z)), float(np.float32(3e-5))
+    want = x0f * K * (bnd ** 2 - a ** 2) / (2 * oracle.HC * (1 + zf))
+    assert np.max(np.abs(f - want)) <= 1e-5 * want
+    assert np.max(np.abs(J[:, 0] + want / (1 + zf))) <= 1e-4 * want
+    ctx.close()
+
+
 # ----------------------------------------------------------------------------- edge cases
 
 def test_edge_cases(ctx6, o6, torch, sb, model):

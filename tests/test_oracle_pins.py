@@ -282,6 +282,50 @@ def test_p7_wavelength_linear_trapezoid_error():
     np.testing.assert_allclose(f[0], exact + corr, rtol=1e-12)
 
 
+def test_p7_midpoint_rule_closed_forms():
+    """Midpoint rule (the quadrature option): exact on the flat top-hat (linear integrand), and on a
+    quadratic integrand its error is -1/2 of the trapezoid's: midpoint = exact - (b-a) Delta^2 g''/24."""
+    K = 0.75
+    md = const_model(K, cl=(-0.9, 0.1, 0.01))
+    a, bnd = 4000.0, 5230.0
+    o = oracle.Oracle(md, [synth.tophat_band(a, bnd)], rule="midpoint")
+    x0, z = 3e-5, 0.4
+    bt = one_sn_batch(np.float32([3.0, 17.25]), 0, z=z, t0=1.0, x0=x0, x1=0.0, c=0.0)
+    zf = float(np.float32(z))
+    want = float(np.float32(x0)) * K * (bnd ** 2 - a ** 2) / (2 * HC * (1 + zf))
+    np.testing.assert_allclose(o.bandflux(bt), want, rtol=1e-13)
+    # quadratic integrand: M0 linear in the rest wavelength
+    Kl, al, be = 1.0, 0.5, 2e-4
+    mu = 2000.0 + 10.0 * np.arange(721)
+    m0 = (Kl * (al + be * mu))[None, :] * np.ones((71, 1))
+    ml = synth.Model(m0=m0, m1=np.zeros((71, 721)), cl_coef=np.zeros(1))
+    a, bnd, spacing = 4100.0, 5350.0, 5.0
+    zq, x0q = 0.3, 1e-5
+    bq = one_sn_batch([4.0], 0, z=zq, t0=0.0, x0=x0q, x1=0.0, c=0.0)
+    zf, x0f = float(np.float32(zq)), float(np.float32(x0q))
+    s = 1 / (1 + zf)
+    A = x0f * s
+    N = int(np.ceil((bnd - a) / spacing))
+    D = (bnd - a) / N
+    exact = A * Kl / HC * (al * (bnd ** 2 - a ** 2) / 2 + be * s * (bnd ** 3 - a ** 3) / 3)
+    g2 = 2 * A * Kl * be * s / HC            # second derivative of the integrand in lambda
+    mid = oracle.Oracle(ml, [synth.tophat_band(a, bnd)], spacing=spacing, rule="midpoint").bandflux(bq)[0]
+    trap = oracle.Oracle(ml, [synth.tophat_band(a, bnd)], spacing=spacing).bandflux(bq)[0]
+    np.testing.assert_allclose(mid, exact - (bnd - a) * D ** 2 * g2 / 24, rtol=1e-12)
+    np.testing.assert_allclose(trap - exact, -2 * (mid - exact), rtol=1e-8)
+
+
+def test_midpoint_grid_nodes_and_weights():
+    """Midpoint grid: the N interval midpoints, weight Delta each, summing to U - L."""
+    b = synth.make_bands(6)[2]
+    lam, T, w = oracle.band_grid(b.wave, b.trans, 5.0, rule="midpoint")
+    lt, _, wt = oracle.band_grid(b.wave, b.trans, 5.0)
+    assert len(lam) == len(lt) - 1
+    np.testing.assert_allclose(lam, 0.5 * (lt[:-1] + lt[1:]), rtol=0, atol=1e-9)
+    np.testing.assert_allclose(w.sum(), b.wave[-1] - b.wave[0], rtol=1e-14)
+    np.testing.assert_allclose(T, np.interp(lam, b.wave, b.trans), rtol=0, atol=0)
+
+
 # ----------------------------------------------------------------------------- P8 quadrature convergence
 
 def test_p8_quadrature_converges_to_quad(model):
