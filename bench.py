@@ -254,7 +254,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--sweep-samples", type=int, default=1 << 20)
-    ap.add_argument("--legs", default="fwd,sweep,big,serve")
+    ap.add_argument("--legs", default="one,fwd,sweep,big,serve")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this size (for calibrating HBM byte counters)")
     args = ap.parse_args()
@@ -342,6 +342,10 @@ def main():
         result["copy_probe_bytes"] = n * 4
         del src, dst
 
+    if "one" in legs:
+        result["one_sn"] = one_sn_leg(torch, saltbf, model, dv)
+        log(f"one_sn: {result['one_sn']}")
+
     if "fwd" in legs:
         d_nochi = {k: D[k] for k in ("z", "t0", "x0", "x1", "c", "t", "band", "sn_offsets")}
         out = torch.empty(n_obs, device="cuda")
@@ -409,6 +413,36 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def one_sn_leg(torch, saltbf, model, dv, calls=200):
+    """One supernova, 40 observations in 4 bands: latency of one call, launch included (host clock
+    from the call to the end of a synchronisation), forward and forward + adjoint."""
+    ctx = saltbf.Context.from_model(model, synth.make_bands(4))
+    b = synth.one_sn_40_obs()
+    D = dict(z=dv(b.z), t0=dv(b.t0), x0=dv(b.x0), x1=dv(b.x1), c=dv(b.c), t=dv(b.t), band=dv(b.band),
+             sn_offsets=dv(b.sn_offsets))
+    out = torch.empty(b.n_obs, device="cuda")
+    grad = torch.empty((1, 5), device="cuda")
+    cot = dv(np.ones(b.n_obs, np.float32))
+    res = {"n_obs": b.n_obs}
+    for name, fn in (("fwd", ctx.prepare_bandflux(**D, out=out)),
+                     ("fwd_adj", ctx.prepare_bandflux_vjp(**D, cotangent=cot, grad=grad, want_flux=True))):
+        for _ in range(20):
+            fn()
+        torch.cuda.synchronize()
+        lat = np.empty(calls)
+        for i in range(calls):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            lat[i] = time.perf_counter() - t0
+        durs, _ = time_launches(torch, fn, calls, 5)
+        res[name] = {"p50_us": float(np.percentile(lat, 50) * 1e6), "p99_us": float(np.percentile(lat, 99) * 1e6),
+                     "kernel_us": float(durs.mean() * 1e3)}
+    ctx.device_check()
+    ctx.close()
+    return res
+
+
 def serve_leg(torch, saltbf, model, bands, seconds, **config):
     """Poisson arrivals at 2,000 req/s: submit each request at its arrival time, collect p50/p99.
     config: sb_config overrides for the serving context."""
@@ -453,7 +487,7 @@ def serve_leg(torch, saltbf, model, bands, seconds, **config):
     return {"requests": n_req, "rate_req_s": rate, "completed_ok": ok, "fits_per_s": len(done) / span,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_queue_ms": float(queue.mean()), "ticks": stats["ticks"],
-            "mean_active_slots_per_tick": None}
+            "mean_active_slots_per_tick": stats["slot_ticks"] / max(1, stats["ticks"])}
 
 
 if __name__ == "__main__":

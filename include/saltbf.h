@@ -199,7 +199,12 @@ typedef struct {
   const float *data, *sigma; /* host [n_obs], sigma > 0 */
   float z;                   /* fixed */
   float t0, x0, x1, c;       /* starting point, x0 > 0 */
+  uint32_t free_mask;        /* parameters the fit varies: an OR of SB_FREE_*; 0 means SB_FREE_ALL.
+                                The others stay at their starting values (the LM system is solved
+                                over the free parameters only).  Other bits: SB_ERR_ARG. */
 } sb_fit_request;
+
+enum { SB_FREE_T0 = 1, SB_FREE_X0 = 2, SB_FREE_X1 = 4, SB_FREE_C = 8, SB_FREE_ALL = 15 };
 
 typedef struct {
   sb_status status;          /* SB_OK, SB_PENDING, SB_CANCELLED, SB_FIT_DIVERGED */
@@ -232,6 +237,7 @@ typedef struct {
   int32_t active_slots;        /* resident on the device */
   int64_t bytes_in_use, budget_bytes;
   double busy_seconds;         /* host time with at least one fit resident */
+  int64_t slot_ticks;          /* fits run, summed over launches (slot_ticks / ticks: mean fits per launch) */
 } sb_stats_t;
 
 sb_status sb_stats(sb_ctx *ctx, sb_stats_t *out);

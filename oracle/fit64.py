@@ -15,7 +15,10 @@ Levenberg-Marquardt damped Gauss-Newton iteration, written here step by step:
   (lambda /= 10), otherwise keeps q (lambda *= 10); a non-positive Cholesky
   pivot counts as a rejected step; lambda stays within [1e-9, 1e9];
 * exactly ``iters`` iterations (default 50) after the evaluation at the
-  starting point, lambda starts at 1e-3.
+  starting point, lambda starts at 1e-3;
+* a subset of the four parameters may be held at its starting value: the
+  damped system is then the one of the free parameters alone (the rows and
+  columns of H and the entries of g that belong to them).
 """
 from __future__ import annotations
 
@@ -27,7 +30,7 @@ LAMBDA_MIN, LAMBDA_MAX = 1e-9, 1e9
 
 
 def _cholesky_solve4(A, b):
-    """Solve A x = b for a symmetric 4x4 A by Cholesky; None if a pivot is not positive."""
+    """Solve A x = b for a symmetric n x n A (n <= 4) by Cholesky; None if a pivot is not positive."""
     n = len(b)
     L = np.zeros((n, n))
     for i in range(n):
@@ -65,9 +68,11 @@ class FitOracle:
         g = J.T @ (w * r)
         return chi2, H, g
 
-    def fit(self, batch, z, theta0, data, inv_sigma2, iters=50, lambda0=1e-3):
-        """LM fit from theta0 = (t0, x0, x1, c).  Returns dict(theta, chi2, n_accept, status)."""
+    def fit(self, batch, z, theta0, data, inv_sigma2, iters=50, lambda0=1e-3, free=(True, True, True, True)):
+        """LM fit from theta0 = (t0, x0, x1, c), varying the parameters whose ``free`` flag is set.
+        Returns dict(theta, chi2, n_accept, status)."""
         t0, x0, x1, c = [float(v) for v in theta0]
+        fr = np.flatnonzero(np.asarray(free, bool))
         q = np.array([t0, np.log(x0), x1, c])
         chi2, H, g = self.evaluate(batch, z, q, data, inv_sigma2)
         if not np.isfinite(chi2):
@@ -75,12 +80,14 @@ class FitOracle:
         lam = lambda0
         n_acc = 0
         for _ in range(iters):
-            A = H + lam * np.diag(np.diag(H))
-            delta = _cholesky_solve4(A, g)
+            Hf = H[np.ix_(fr, fr)]
+            A = Hf + lam * np.diag(np.diag(Hf))
+            delta = _cholesky_solve4(A, g[fr])
             if delta is None:
                 lam = min(lam * 10.0, LAMBDA_MAX)
                 continue
-            qt = q + delta
+            qt = q.copy()
+            qt[fr] += delta
             chi2_t, H_t, g_t = self.evaluate(batch, z, qt, data, inv_sigma2)
             if np.isfinite(chi2_t) and chi2_t < chi2:
                 q, chi2, H, g = qt, chi2_t, H_t, g_t

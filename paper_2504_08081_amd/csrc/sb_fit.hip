@@ -127,17 +127,27 @@ __device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, cons
   block_sum<15, NW>(out, S.red);
 }
 
-// Solve (H + lambda diag H) d = g by Cholesky.  False if a pivot is not positive.
-__device__ bool damped_solve(const float* H, const float* g, float lambda, float* d) {
+// Solve (H + lambda diag H) d = g by Cholesky over the free parameters (free_mask
+// bit i set): a held parameter's row and column become those of the identity and
+// its right-hand side 0, which decouples it with d_i = 0 and leaves the free block
+// as it was.  False if a pivot is not positive.
+__device__ bool damped_solve(const float* H, const float* g, float lambda, int free_mask, float* d) {
   float a[4][4];
+  float rhs[4];
   int k = 0;
   for (int i = 0; i < 4; ++i)
     for (int j = i; j < 4; ++j) {
-      a[i][j] = H[k];
-      a[j][i] = H[k];
+      const bool keep = ((free_mask >> i) & 1) && ((free_mask >> j) & 1);
+      const float v = keep ? H[k] : (i == j ? 1.f : 0.f);
+      a[i][j] = v;
+      a[j][i] = v;
       ++k;
     }
-  for (int i = 0; i < 4; ++i) a[i][i] = fmaf(lambda, a[i][i], a[i][i]);
+  for (int i = 0; i < 4; ++i) {
+    const bool fr = (free_mask >> i) & 1;
+    if (fr) a[i][i] = fmaf(lambda, a[i][i], a[i][i]);
+    rhs[i] = fr ? g[i] : 0.f;
+  }
   float l[4][4] = {};
   for (int i = 0; i < 4; ++i) {
     for (int j = 0; j <= i; ++j) {
@@ -153,7 +163,7 @@ __device__ bool damped_solve(const float* H, const float* g, float lambda, float
   }
   float y[4];
   for (int i = 0; i < 4; ++i) {
-    float sum = g[i];
+    float sum = rhs[i];
     for (int p = 0; p < i; ++p) sum -= l[i][p] * y[p];
     y[i] = sum / l[i][i];
   }
@@ -180,7 +190,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F)
   float z;
   // the LM state; every thread holds the same values
   float q[4], H[10], g[4], lambda, chi2;
-  int iter, n_acc, status;
+  int iter, n_acc, status, free_mask;
   if (adm >= 0) {
     // first launch of this fit: move its observations from the inbox to the arena
     const AdmitHeader h = F.hdr[adm];
@@ -201,6 +211,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F)
     q[1] = h.lnx0;
     q[2] = h.x1;
     q[3] = h.c;
+    free_mask = h.free_mask;
 #pragma unroll
     for (int k = 0; k < 10; ++k) H[k] = 0.f;
 #pragma unroll
@@ -228,6 +239,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F)
     iter = sl->iter;
     n_acc = sl->n_accept;
     status = sl->status;
+    free_mask = sl->free_mask;
   }
   const double s64 = 1.0 / (1.0 + (double)z);
   float out[15];
@@ -249,7 +261,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F)
   for (int it = 0; it < F.iters; ++it) {
     if (uni((status != SB_OK || iter >= F.fit_iters) ? 1 : 0)) break;
     float d[4];
-    const int solved = uni(damped_solve(H, g, lambda, d) ? 1 : 0);
+    const int solved = uni(damped_solve(H, g, lambda, free_mask, d) ? 1 : 0);
     if (!solved) {
       lambda = fminf(lambda * 10.f, 1e9f);
       iter += 1;
@@ -281,7 +293,8 @@ __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F)
     st.iter = iter;
     st.n_accept = n_acc;
     st.status = status;
-    st.pad_[0] = st.pad_[1] = st.pad_[2] = 0;
+    st.free_mask = free_mask;
+    st.pad_[0] = st.pad_[1] = 0;
     st.z = z;
     for (int k = 0; k < 4; ++k) st.q[k] = q[k];
     st.lambda = lambda;

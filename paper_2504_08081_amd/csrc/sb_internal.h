@@ -73,7 +73,8 @@ struct FitSlot {
   int iter;         // LM iterations done; -1 = not yet evaluated at the start point
   int n_accept;
   int status;       // SB_OK / SB_FIT_DIVERGED
-  int pad_[3];
+  int free_mask;    // SB_FREE_* bits of the parameters the fit varies
+  int pad_[2];
   float z;
   float q[4];       // t0, ln x0, x1, c
   float lambda;
@@ -90,7 +91,8 @@ struct AdmitHeader {
   int n_obs;
   int src_off;       // offset of its observations in the inbox arrays
   float z, t0, lnx0, x1, c;
-  int pad_[3];
+  int free_mask;
+  int pad_[2];
 };
 
 struct KFit {

@@ -140,6 +140,7 @@ sb_status Server::submit(const sb_fit_request* r, uint64_t* ticket) {
   if (!std::isfinite(r->z) || !(r->z > -1.f) || !std::isfinite(r->t0) || !std::isfinite(r->x1) ||
       !std::isfinite(r->c) || !std::isfinite(r->x0) || !(r->x0 > 0.f))
     return set_error(SB_ERR_ARG, "sb_fit_submit: bad starting parameters");
+  if (r->free_mask & ~(uint32_t)SB_FREE_ALL) return set_error(SB_ERR_ARG, "sb_fit_submit: unknown free_mask bits");
   const double opz = 1.0 + (double)r->z;
   for (int i = 0; i < r->n_obs; ++i) {
     const int b = r->band[i];
@@ -166,6 +167,7 @@ sb_status Server::submit(const sb_fit_request* r, uint64_t* ticket) {
   q.x0 = r->x0;
   q.x1 = r->x1;
   q.c = r->c;
+  q.free_mask = r->free_mask == 0 ? SB_FREE_ALL : (int)r->free_mask;
   q.bytes = bytes;
   q.t_submit = now_seconds();
   {
@@ -248,6 +250,7 @@ void Server::stats(sb_stats_t* out) {
   out->bytes_in_use = bytes_in_use_;
   out->budget_bytes = ctx_->cfg.hbm_budget_bytes;
   out->busy_seconds = busy_s_;
+  out->slot_ticks = n_slot_ticks_;
 }
 
 void Server::release_slot(int s) {
@@ -295,6 +298,8 @@ bool Server::prepare_tick(int parity, std::vector<Retire>& retire, size_t& blob_
     sl.n_obs = n;
     sl.ticks_left = ticks_per_fit;
     sl.bytes = q.bytes;
+    sl.free_mask = q.free_mask;
+    sl.x0 = q.x0;
     bytes_in_use_ += q.bytes;
     ++n_active_slots_;
     ++n_admitted_;
@@ -349,6 +354,7 @@ bool Server::prepare_tick(int parity, std::vector<Retire>& retire, size_t& blob_
     h.lnx0 = (float)std::log((double)q.x0);
     h.x1 = q.x1;
     h.c = q.c;
+    h.free_mask = q.free_mask;
     hdr.push_back(h);
     src += sl.n_obs;
   }
@@ -403,7 +409,7 @@ void Server::finish_tick(int parity) {
           res.status = st.status;
           res.z = st.z;
           res.t0 = st.q[0];
-          res.x0 = std::exp(st.q[1]);
+          res.x0 = (slots_[r.slot].free_mask & SB_FREE_X0) ? std::exp(st.q[1]) : slots_[r.slot].x0;
           res.x1 = st.q[2];
           res.c = st.q[3];
           res.chi2 = st.chi2;
@@ -497,6 +503,7 @@ void Server::loop() {
         ticks_[parity].pending = true;
         ticks_[parity].retire = std::move(retire);
         ++n_ticks_;
+        n_slot_ticks_ += n_active;
       }
     }
     if (ticks_[1 - parity].pending) finish_tick(1 - parity);

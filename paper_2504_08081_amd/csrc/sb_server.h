@@ -45,6 +45,7 @@ class Server {
     std::vector<float> t, data, w;
     std::vector<int> band;
     float z, t0, x0, x1, c;
+    int free_mask;
     double t_submit;
     int64_t bytes;
   };
@@ -62,6 +63,8 @@ class Server {
     int n_obs = 0;
     int ticks_left = 0;
     int64_t bytes = 0;
+    int free_mask = SB_FREE_ALL;
+    float x0 = 0.f;     // starting x0, reported as given when x0 is held fixed
   };
   struct Retire {       // slot to release once its last launch has completed
     int slot;
@@ -96,7 +99,8 @@ class Server {
   int64_t bytes_in_use_ = 0;
 
   // stats
-  int64_t n_submitted_ = 0, n_admitted_ = 0, n_completed_ = 0, n_cancelled_ = 0, n_rejected_ = 0, n_ticks_ = 0;
+  int64_t n_submitted_ = 0, n_admitted_ = 0, n_completed_ = 0, n_cancelled_ = 0, n_rejected_ = 0, n_ticks_ = 0,
+          n_slot_ticks_ = 0;
   int n_active_slots_ = 0;
   double busy_s_ = 0.0;
 

@@ -21,6 +21,7 @@ SB_ERR_ARG, SB_ERR_RANGE, SB_ERR_DEVICE, SB_ERR_NOMEM = -1, -2, -3, -4
 SB_ERR_BUDGET, SB_ERR_STATE, SB_ERR_NOTFOUND = -5, -6, -7
 SB_OBS_BROADCAST, SB_OUT_CHI2 = 1, 2
 SB_QUAD_TRAPEZOID, SB_QUAD_MIDPOINT = 0, 1
+SB_FREE_T0, SB_FREE_X0, SB_FREE_X1, SB_FREE_C, SB_FREE_ALL = 1, 2, 4, 8, 15
 SB_MAX_BANDS, SB_MAX_BAND_POINTS, SB_N_PARAMS = 64, 2048, 5
 
 EXPORTED = (
@@ -63,7 +64,7 @@ class FitRequest(ctypes.Structure):
     _fields_ = [("n_obs", ctypes.c_int32), ("t", ctypes.c_void_p), ("band", ctypes.c_void_p),
                 ("data", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
                 ("z", ctypes.c_float), ("t0", ctypes.c_float), ("x0", ctypes.c_float),
-                ("x1", ctypes.c_float), ("c", ctypes.c_float)]
+                ("x1", ctypes.c_float), ("c", ctypes.c_float), ("free_mask", ctypes.c_uint32)]
 
 
 class FitResult(ctypes.Structure):
@@ -81,7 +82,7 @@ class Stats(ctypes.Structure):
                 ("cancelled", ctypes.c_int64), ("rejected", ctypes.c_int64), ("ticks", ctypes.c_int64),
                 ("queue_depth", ctypes.c_int32), ("active_slots", ctypes.c_int32),
                 ("bytes_in_use", ctypes.c_int64), ("budget_bytes", ctypes.c_int64),
-                ("busy_seconds", ctypes.c_double)]
+                ("busy_seconds", ctypes.c_double), ("slot_ticks", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -366,13 +367,14 @@ class Context:
         _check(lib().sb_device_check(self._h, _stream(stream)), "sb_device_check")
 
     # ------------------------------------------------------------------ serving
-    def fit_submit(self, t, band, data, sigma, z, t0, x0, x1, c) -> int:
+    def fit_submit(self, t, band, data, sigma, z, t0, x0, x1, c, free_mask=0) -> int:
+        """Queue one fit; free_mask: an OR of SB_FREE_* (0: all four parameters free)."""
         t = np.ascontiguousarray(t, np.float32)
         band = np.ascontiguousarray(band, np.int32)
         data = np.ascontiguousarray(data, np.float32)
         sigma = np.ascontiguousarray(sigma, np.float32)
         r = FitRequest(len(t), t.ctypes.data, band.ctypes.data, data.ctypes.data, sigma.ctypes.data,
-                       z, t0, x0, x1, c)
+                       z, t0, x0, x1, c, free_mask)
         tk = ctypes.c_uint64(0)
         _check(lib().sb_fit_submit(self._h, ctypes.byref(r), ctypes.byref(tk)), "sb_fit_submit")
         return tk.value

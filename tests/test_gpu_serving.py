@@ -90,6 +90,47 @@ def test_fits_match_oracle(sb, o6, model, bands6, requests):
     ctx.close()
 
 
+@pytest.mark.parametrize("mask", [7, 13, 11])
+def test_fits_with_held_parameters(sb, o6, model, bands6, requests, mask):
+    """free_mask: the held parameters come back exactly as submitted, and the free ones match the
+    FP64 LM fit over the same subset (within 1e-2 of their uncertainty, chi2 within 1e-4).  The
+    fits share launches with all-free fits of the same requests."""
+    ctx = sb.Context.from_model(model, bands6)
+    items = requests[12:20]
+    tk_held = [ctx.fit_submit(r.t, r.band, d, sig, r.z, *r.theta_init, free_mask=mask) for r, d, sig, _ in items]
+    tk_all = [submit(ctx, it) for it in items]
+    held = [ctx.fit_wait(tk, 60.0) for tk in tk_held]
+    full = [ctx.fit_wait(tk, 60.0) for tk in tk_all]
+    assert all(x is not None for x in held + full)
+    fo = oracle.FitOracle(o6)
+    free = [bool(mask >> k & 1) for k in range(4)]
+    fr = np.flatnonzero(free)
+    worst = 0.0
+    for (r, d, sig, w), g, ga in zip(items, held, full):
+        assert g.status == sb.SB_OK and g.iters == 50 and ga.status == sb.SB_OK
+        start = np.float32(r.theta_init)
+        got = np.float32([g.t0, g.x0, g.x1, g.c])
+        for k in range(4):
+            if not free[k]:
+                assert got[k] == start[k], (k, got, start)
+        ref = fo.fit(single_batch(r), r.z, r.theta_init, d, w, free=free)
+        th = ref["theta"]
+        q64 = np.array([th[0], np.log(th[1]), th[2], th[3]])
+        qg = np.array([g.t0, np.log(g.x0), g.x1, g.c])
+        _, H, _ = fo.evaluate(single_batch(r), r.z, q64, d, w)
+        sig_q = np.sqrt(np.diag(np.linalg.inv(H[np.ix_(fr, fr)])))
+        dev = np.abs(qg[fr] - q64[fr]) / sig_q
+        worst = max(worst, dev.max())
+        assert dev.max() <= 1e-2, (dev, g.as_dict(), ref)
+        assert abs(g.chi2 - ref["chi2"]) <= 1e-4 * ref["chi2"]
+        assert g.chi2 >= ga.chi2 * (1 - 1e-5)   # holding parameters cannot fit better
+    print(f"free_mask {mask}: max |dq|/sigma_q = {worst:.2e}")
+    with pytest.raises(sb.SaltBFError):
+        r, d, sig, _ = items[0]
+        ctx.fit_submit(r.t, r.band, d, sig, r.z, *r.theta_init, free_mask=16)
+    ctx.close()
+
+
 def test_fits_with_single_wave_workgroups(sb, o6, model, bands6, requests):
     """A 12 KiB LDS limit makes the fit kernel run one wave per fit; fits still match the oracle."""
     ctx = sb.Context.from_model(model, bands6, lds_limit_bytes=12 * 1024)

@@ -431,6 +431,59 @@ def test_p11_fit_recovers_truth(model, bands6):
         assert abs(th[2] - tt[2]) < 1e-5 and abs(th[3] - tt[3]) < 1e-6
 
 
+@pytest.mark.parametrize("held", [3, 2, 0])
+def test_p11_fit_with_a_held_parameter(model, bands6, held):
+    """A parameter held at its true value stays there exactly and the free ones are recovered
+    from noise-free data, as with all four free."""
+    o = oracle.Oracle(model, bands6)
+    fo = oracle.FitOracle(o)
+    r = synth.fit_requests(1, k=43)[0]
+    b = synth.Batch(np.float32([r.z]), np.float32([r.theta_true[0]]), np.float32([r.theta_true[1]]),
+                    np.float32([r.theta_true[2]]), np.float32([r.theta_true[3]]), r.t, r.band,
+                    np.int32([0, len(r.t)]))
+    f = o.bandflux(b)
+    _, sig, w = synth.make_data(f, b.sn_offsets, np.zeros(len(f)))
+    start = np.array(r.theta_init, np.float64)
+    start[held] = r.theta_true[held]
+    free = [k != held for k in range(4)]
+    res = fo.fit(b, r.z, start, f, w, free=free)
+    th, tt = res["theta"], np.asarray(r.theta_true, np.float64)
+    assert th[held] == start[held] or (held == 1 and abs(th[1] / start[1] - 1) < 1e-15)
+    assert res["chi2"] < 1e-8
+    assert abs(th[0] - tt[0]) < 1e-5 and abs(th[1] / tt[1] - 1) < 1e-6
+    assert abs(th[2] - tt[2]) < 1e-5 and abs(th[3] - tt[3]) < 1e-6
+
+
+def test_p11_held_parameters_on_linear_least_squares():
+    """On a linear model the fit with some parameters held converges to the weighted
+    least-squares solution over the free columns, the held values moved to the data side
+    (numpy.linalg.lstsq)."""
+    g = np.random.default_rng(12)
+    X = g.normal(size=(40, 4))
+    d = g.normal(size=40)
+    w = g.uniform(0.5, 2.0, 40)
+
+    class Lin(oracle.FitOracle):
+        def __init__(self):
+            pass
+
+        def evaluate(self, batch, z, q, data, inv_sigma2):
+            r = d - X @ q
+            return float(np.sum(w * r * r)), X.T @ (w[:, None] * X), X.T @ (w * r)
+
+    q0 = np.array([0.3, np.log(2.0), -1.0, 0.5])
+    for free in ([True, True, False, True], [False, True, True, False], [True, False, False, False]):
+        fr = np.flatnonzero(free)
+        hd = np.flatnonzero(~np.asarray(free))
+        sw = np.sqrt(w)
+        rhs = d - X[:, hd] @ q0[hd]
+        sol = np.linalg.lstsq(sw[:, None] * X[:, fr], sw * rhs, rcond=None)[0]
+        res = Lin().fit(None, 0.0, [q0[0], np.exp(q0[1]), q0[2], q0[3]], d, w, iters=60, free=free)
+        q = np.array([res["theta"][0], np.log(res["theta"][1]), res["theta"][2], res["theta"][3]])
+        np.testing.assert_allclose(q[fr], sol, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(q[hd], q0[hd], rtol=1e-15, atol=0)
+
+
 def test_p11_lm_iterates_on_linear_least_squares():
     """On a linear model every LM iterate has a closed form: q1 = q0 + (H + lam0 diag H)^-1 g,
     lambda shrinks by 10 after an accepted step and grows by 10 after a rejected one."""
