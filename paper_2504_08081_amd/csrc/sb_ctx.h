@@ -27,7 +27,6 @@ struct sb_ctx {
   sbk::KModel km{};
   double wave_lo = 0, wave_hi = 0;     // surface wavelength range (Angstrom)
   float2* d_surf = nullptr;
-  float4* d_surf4 = nullptr;
   float2* d_pts = nullptr;
   int* d_npts = nullptr;
   int* d_err = nullptr;
@@ -47,7 +46,6 @@ struct sb_ctx {
     t.npts = d_npts;
     t.max_pts = max_pts;
     t.jcap = jcap;
-    t.surf4 = d_surf4;
     t.surf_bytes = (int)((size_t)(km.n_wave + sbk::SURF_PAD_COLS) * km.row_pad * sizeof(float2));
     t.lds_limit = (int)max_lds;
     return t;

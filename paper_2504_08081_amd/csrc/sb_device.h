@@ -289,23 +289,65 @@ __device__ inline void tail_cols(float (&acc)[4][4], const typename ModeInfo<MOD
     if (u < rem) col_step<MODE>(acc[u & 3], g[u], v[u], x1);
 }
 
-// Adjoint form of the row projections on the difference surface: nodes and
-// first differences (M0, M1, D0, D1) of the lane's row in 4 consecutive columns.
-__device__ inline void load_cols4d(float4 (&v)[4], __amdgpu_buffer_rsrc_t rs, unsigned loff, int col, int cstride) {
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-    v[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)loff, col + u * cstride, 0));
+// One window column j of the adjoint's row projections from the lane's row
+// nodes cur = (M0, M1)(j), with the previous column's nodes prev and difference
+// weight gdp: the first difference D(j-1) = M(j) - M(j-1) is formed here (one
+// FP32 subtraction per surface, as exact as a stored difference) and its term
+// goes to the previous column's chain, after that column's own terms, so every
+// chain sums in column order.  Chains are window columns mod 4 (U = this one's).
+template <int U>
+__device__ inline void col_step_d(float (&acc)[4][4], float4 g, float2 cur, float2& prev, float& gdp, float x1) {
+  constexpr int P = (U + 3) & 3;
+  const float dx = fmaf(x1, cur.y - prev.y, cur.x - prev.x);
+  acc[P][3] = fmaf(gdp, dx, acc[P][3]);
+  const float mx = fmaf(x1, cur.y, cur.x);
+  acc[U][0] = fmaf(g.x, mx, acc[U][0]);
+  acc[U][1] = fmaf(g.x, cur.y, acc[U][1]);
+  acc[U][2] = fmaf(g.y, mx, acc[U][2]);
+  acc[U][3] = fmaf(g.z, mx, acc[U][3]);
+  prev = cur;
+  gdp = g.w;
 }
 
-// One window column of the adjoint's row projections from (M0, M1, D0, D1).
-__device__ inline void col_step_d(float (&acc)[4], float4 g, float4 md, float x1) {
-  const float mx = fmaf(x1, md.y, md.x);
-  const float dx = fmaf(x1, md.w, md.z);
-  acc[0] = fmaf(g.x, mx, acc[0]);
-  acc[1] = fmaf(g.x, md.y, acc[1]);
-  acc[2] = fmaf(g.y, mx, acc[2]);
-  acc[3] = fmaf(g.z, mx, acc[3]);
-  acc[3] = fmaf(g.w, dx, acc[3]);
+template <int CW>
+__device__ inline void chunk_cols_d(float (&acc)[4][4], const float4* g, const float2 (&v)[CW], float2& prev,
+                                    float& gdp, float x1) {
+  static_assert(CW == 4, "one chunk is one column per chain");
+  col_step_d<0>(acc, g[0], v[0], prev, gdp, x1);
+  col_step_d<1>(acc, g[1], v[1], prev, gdp, x1);
+  col_step_d<2>(acc, g[2], v[2], prev, gdp, x1);
+  col_step_d<3>(acc, g[3], v[3], prev, gdp, x1);
+}
+
+// The difference term of the window's last column, on chain P, from the column
+// after the window, nx.  Its weight is zero; the term is kept so that every chain
+// ends as the column loop leaves it.
+template <int P>
+__device__ inline void close_chain(float (&acc)[4][4], float2 nx, float2 prev, float gdp, float x1) {
+  const float dx = fmaf(x1, nx.y - prev.y, nx.x - prev.x);
+  acc[P][3] = fmaf(gdp, dx, acc[P][3]);
+}
+
+// The last rem (< 4) window columns, held in v[0 .. rem-1], and the closing
+// difference term from v[rem] (branches on the uniform rem, static indices only).
+__device__ inline void tail_cols_d(float (&acc)[4][4], const float4* g, const float2 (&v)[4], int rem,
+                                   float2& prev, float& gdp, float x1) {
+  if (rem == 0) {
+    close_chain<3>(acc, v[0], prev, gdp, x1);
+    return;
+  }
+  col_step_d<0>(acc, g[0], v[0], prev, gdp, x1);
+  if (rem == 1) {
+    close_chain<0>(acc, v[1], prev, gdp, x1);
+    return;
+  }
+  col_step_d<1>(acc, g[1], v[1], prev, gdp, x1);
+  if (rem == 2) {
+    close_chain<1>(acc, v[2], prev, gdp, x1);
+    return;
+  }
+  col_step_d<2>(acc, g[2], v[2], prev, gdp, x1);
+  close_chain<2>(acc, v[3], prev, gdp, x1);
 }
 
 // Rest wavelength mu = lam s of a quadrature point and its wavelength cell j0
@@ -446,42 +488,38 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   //     and the padding columns after the grid keep every prefetch in bounds.
   const int nrow = rhi - rlo + 1;
   if constexpr (MODE == VJP) {
-    // the adjoint reads the difference surface, 4 columns per chunk (16 bytes per lane and column)
-    const int cstride = m.row_pad * (int)sizeof(float4);
+    // the adjoint reads the node surface like the other modes and forms the
+    // first differences on the way (see col_step_d)
+    const int cstride = m.row_pad * (int)sizeof(float2);
     const int n4 = J >> 2, rem = J & 3;
     const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc((void*)tb.surf4, 0, 2 * tb.surf_bytes, BUF_RSRC_WORD3);
+        __builtin_amdgcn_make_buffer_rsrc((void*)tb.surf, 0, tb.surf_bytes, BUF_RSRC_WORD3);
     for (int rb = 0; rb < nrow; rb += 64) {
       const int a = rlo + rb + lane;
-      const unsigned loff = rb + lane < nrow ? (unsigned)a * (unsigned)sizeof(float4) : BUF_OFF_NONE;
+      const unsigned loff = rb + lane < nrow ? (unsigned)a * (unsigned)sizeof(float2) : BUF_OFF_NONE;
       const int cb = j_lo * cstride;
       float acc[4][4];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[u][r] = 0.f;
-      float4 A[4], B[4];
-      load_cols4d(A, rs, loff, cb, cstride);
+      float2 prev = make_float2(0.f, 0.f);
+      float gdp = 0.f;
+      float2 A[4], B[4];
+      load_cols<4>(A, rs, loff, cb, cstride);
       int c = 0;
       for (; c + 2 <= n4; c += 2) {
-        load_cols4d(B, rs, loff, cb + (4 * c + 4) * cstride, cstride);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) col_step_d(acc[u], Gv[4 * c + u], A[u], x1);
-        load_cols4d(A, rs, loff, cb + (4 * c + 8) * cstride, cstride);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) col_step_d(acc[u], Gv[4 * c + 4 + u], B[u], x1);
+        load_cols<4>(B, rs, loff, cb + (4 * c + 4) * cstride, cstride);
+        chunk_cols_d<4>(acc, Gv + 4 * c, A, prev, gdp, x1);
+        load_cols<4>(A, rs, loff, cb + (4 * c + 8) * cstride, cstride);
+        chunk_cols_d<4>(acc, Gv + 4 * c + 4, B, prev, gdp, x1);
       }
       if (c < n4) {
-        load_cols4d(B, rs, loff, cb + (4 * c + 4) * cstride, cstride);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) col_step_d(acc[u], Gv[4 * c + u], A[u], x1);
-#pragma unroll
-        for (int u = 0; u < 3; ++u)
-          if (u < rem) col_step_d(acc[u], Gv[4 * c + 4 + u], B[u], x1);
+        load_cols<4>(B, rs, loff, cb + (4 * c + 4) * cstride, cstride);
+        chunk_cols_d<4>(acc, Gv + 4 * c, A, prev, gdp, x1);
+        tail_cols_d(acc, Gv + 4 * c + 4, B, rem, prev, gdp, x1);
       } else {
-#pragma unroll
-        for (int u = 0; u < 3; ++u)
-          if (u < rem) col_step_d(acc[u], Gv[4 * c + u], A[u], x1);
+        tail_cols_d(acc, Gv + 4 * c, A, rem, prev, gdp, x1);
       }
       if (rb + lane < nrow) {
 #pragma unroll

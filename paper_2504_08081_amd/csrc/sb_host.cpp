@@ -133,7 +133,6 @@ sb_status sb_band_grid(const double* wave, const double* trans, int32_t n, doubl
 static void free_ctx(sb_ctx* c) {
   if (!c) return;
   if (c->d_surf) (void)hipFree(c->d_surf);
-  if (c->d_surf4) (void)hipFree(c->d_surf4);
   if (c->d_pts) (void)hipFree(c->d_pts);
   if (c->d_npts) (void)hipFree(c->d_npts);
   if (c->d_err) (void)hipFree(c->d_err);
@@ -217,20 +216,8 @@ sb_status sb_create(const sb_model_desc* md, const sb_config* cfg_in, int device
       const size_t src = (size_t)a * k.n_wave + j;
       surf[(size_t)j * k.row_pad + a] = make_float2(md->m0[src], md->m1[src]);
     }
-  // the adjoint's copy with the first differences D(j) = M(j+1) - M(j) of each row beside the
-  // nodes: (M0, M1, D0, D1), each difference one FP32 subtraction (the next column of the last
-  // one is a zero padding column)
-  std::vector<float4> surf4(surf.size(), make_float4(0.f, 0.f, 0.f, 0.f));
-  for (int j = 0; j < k.n_wave; ++j)
-    for (int a = 0; a < k.n_phase; ++a) {
-      const float2 cur = surf[(size_t)j * k.row_pad + a];
-      const float2 nxt = surf[(size_t)(j + 1) * k.row_pad + a];
-      const float d0 = nxt.x - cur.x, d1 = nxt.y - cur.y;
-      surf4[(size_t)j * k.row_pad + a] = make_float4(cur.x, cur.y, d0, d1);
-    }
   const size_t pts_bytes = (size_t)SB_MAX_BANDS * SB_MAX_BAND_POINTS * sizeof(float2);
   if ((e = hipMalloc(&c->d_surf, surf.size() * sizeof(float2))) != hipSuccess ||
-      (e = hipMalloc(&c->d_surf4, surf4.size() * sizeof(float4))) != hipSuccess ||
       (e = hipMalloc(&c->d_pts, pts_bytes)) != hipSuccess ||
       (e = hipMalloc(&c->d_npts, SB_MAX_BANDS * sizeof(int))) != hipSuccess ||
       (e = hipMalloc(&c->d_err, sizeof(int))) != hipSuccess) {
@@ -238,7 +225,6 @@ sb_status sb_create(const sb_model_desc* md, const sb_config* cfg_in, int device
     return set_error(SB_ERR_NOMEM, std::string("sb_create: hipMalloc: ") + hipGetErrorString(e));
   }
   if ((e = hipMemcpy(c->d_surf, surf.data(), surf.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(c->d_surf4, surf4.data(), surf4.size() * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemset(c->d_pts, 0, pts_bytes)) != hipSuccess ||
       (e = hipMemset(c->d_npts, 0, SB_MAX_BANDS * sizeof(int))) != hipSuccess ||
       (e = hipMemset(c->d_err, 0, sizeof(int))) != hipSuccess) {

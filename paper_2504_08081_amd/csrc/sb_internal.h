@@ -39,8 +39,7 @@ struct KTables {
   const int* npts;      // [n_bands] node count per band
   int max_pts;          // largest node count over registered bands (sizes the LDS)
   int jcap;             // largest surface window (columns) a band can need for z >= WINDOW_Z_MIN
-  const float4* surf4;  // same layout, (M0, M1, D0, D1) with D(j) = M(j+1) - M(j) (adjoint)
-  int surf_bytes;       // size of surf in bytes (surf4 is twice that)
+  int surf_bytes;       // size of surf in bytes
   int lds_limit;        // dynamic LDS bytes a workgroup may use (host side: picks the waves per workgroup)
 };
 

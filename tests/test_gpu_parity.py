@@ -213,6 +213,40 @@ def test_prepared_calls_match_plain_calls(ctx6, big_batch, torch):
     ctx6.device_check()
 
 
+def test_graph_replays_match_eager(ctx6, big_batch, torch):
+    """Prepared calls captured in a HIP graph (torch.cuda.CUDAGraph on a side stream): every replay
+    equals the eager call bitwise, with eager work and synchronisations between replays, and a
+    replay sees parameter buffers updated in place."""
+    d = to_dev(big_batch, torch)
+    data = torch.ones(big_batch.n_obs, dtype=torch.float32, device="cuda")
+    w = torch.ones(big_batch.n_obs, dtype=torch.float32, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    pv = ctx6.prepare_bandflux_vjp(**d, data=data, inv_sigma2=w, chi2=True, stream=side)
+    pf = ctx6.prepare_bandflux(**d, stream=side)
+    with torch.cuda.stream(side):
+        pv()
+        pf()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        pv()
+        pf()
+        pv()
+    for rep in range(4):
+        g.replay()
+        torch.cuda.synchronize()
+        grad_g, chi_g, f_g = pv.outputs["grad"].clone(), pv.outputs["chi2"].clone(), pf.outputs["out"].clone()
+        a = ctx6.bandflux_vjp(**d, data=data, inv_sigma2=w, chi2=True)
+        f = ctx6.bandflux(**d)
+        torch.cuda.synchronize()
+        assert torch.equal(grad_g, a["grad"]) and torch.equal(chi_g, a["chi2"]), rep
+        assert torch.equal(f_g, f), rep
+        assert torch.isfinite(grad_g).all()
+        d["c"].add_(0.01)    # the next replay reads the updated colours
+    ctx6.device_check()
+
+
 def test_single_wave_workgroups_when_lds_is_short(sb, model, bands6, big_batch, torch):
     """With a 12 KiB LDS limit every kernel runs one wave per workgroup instead of several: the
     per-observation results are bitwise those of the multi-wave kernels (each band's projections are
