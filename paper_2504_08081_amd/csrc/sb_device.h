@@ -138,13 +138,29 @@ __device__ inline PhaseCell phase_cell(float t, float t0, double s, const KModel
   return c;
 }
 
-// Colour law CL(mu) and dCL/dmu.
-__device__ inline void colour_law(float mu, const KModel& m, float& cl, float& dcl) {
+// The colour law's coefficients spread over the lanes of a wave: lane n holds
+// a_(n+1) in .x and (n+1) a_(n+1) in .y (zero past the degree), so that the
+// Horner steps read them with readlane instead of waiting on memory.
+__device__ inline float2 colour_coefs(const KModel& m) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  float2 q = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int n = 0; n < SB_MAX_CL_DEGREE; ++n)
+    if (lane == n) q = make_float2(m.cl[n], m.dcl[n]);
+  return q;
+}
+
+__device__ inline float lane_f(float v, int n) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), n));
+}
+
+// Colour law CL(mu) and dCL/dmu (coefficients q from colour_coefs).
+__device__ inline void colour_law(float mu, const KModel& m, float2 q, float& cl, float& dcl) {
   const float r = (mu - m.cl_b) * m.cl_inv_span;
   float v = 0.f, d = 0.f;
   for (int n = m.cl_deg - 1; n >= 0; --n) {
-    v = fmaf(v, r, m.cl[n]);
-    d = fmaf(d, r, m.dcl[n]);
+    v = fmaf(v, r, lane_f(q.x, n));
+    d = fmaf(d, r, lane_f(q.y, n));
   }
   cl = v * r;
   dcl = d * m.cl_inv_span;
@@ -378,24 +394,29 @@ __device__ inline WaveCell wave_cell(float lam, double s, const KModel& m) {
 // Quadrature point k of a band, (lam_k, W_k) = lw, for a supernova with
 // s = 1/(1+z) and colour c: its fraction x and weight factors P (om_k = W_k
 // exp(c CL(mu_k)), and per mode om_k CL, om_k mu_k c CL', om_k mu_k / dwave)
-// into the wave's scratch.  Returns the point's wavelength cell.
+// into the wave's scratch, if k < np.  Every lane of the wave calls it (the
+// colour law reads its coefficients across lanes).  Returns the point's
+// wavelength cell.
 template <int MODE>
-__device__ inline int point_setup(const KModel& m, double s, float c, float2 lw, int k, const Lds& L) {
+__device__ inline int point_setup(const KModel& m, double s, float c, float2 clq, float2 lw, int k, int np,
+                                  const Lds& L) {
   typedef typename ModeInfo<MODE>::V V;
   const WaveCell w = wave_cell(lw.x, s, m);
   float cl, dcl;
-  colour_law(w.mu, m, cl, dcl);
+  colour_law(w.mu, m, clq, cl, dcl);
   const float om = lw.y * expf(c * cl);
-  V* Pv = (V*)L.P;
-  if constexpr (MODE == FWD) {
-    Pv[k] = om;
-  } else if constexpr (MODE == FIT) {
-    Pv[k] = make_float2(om, om * cl);
-  } else {
-    const float omu = om * w.mu;
-    Pv[k] = make_float4(om, om * cl, omu * (c * dcl), omu * m.inv_dwave);
+  if (k < np) {
+    V* Pv = (V*)L.P;
+    if constexpr (MODE == FWD) {
+      Pv[k] = om;
+    } else if constexpr (MODE == FIT) {
+      Pv[k] = make_float2(om, om * cl);
+    } else {
+      const float omu = om * w.mu;
+      Pv[k] = make_float4(om, om * cl, omu * (c * dcl), omu * m.inv_dwave);
+    }
+    L.x[k] = w.x;
   }
-  L.x[k] = w.x;
   return w.j0;
 }
 
@@ -428,9 +449,15 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   const float2* pts = tb.pts + (size_t)bd * SB_MAX_BAND_POINTS;
   V* Gv = (V*)L.G;
 
+  // the first pass's points, and the band's first and last point (lanes 0 and
+  // 1 of one load), are requested before anything waits on memory
+  float2 cur = lane < np ? pts[lane] : make_float2(0.f, 0.f);
+  const float ends = pts[lane == 0 ? 0 : np - 1].x;
+  const float2 clq = colour_coefs(m);
+
   // the window: the cells of the first and last points (cells are non-decreasing
   // in k, so every point is on the grid if these two are)
-  const WaveCell wf = wave_cell(pts[0].x, s, m), wl = wave_cell(pts[np - 1].x, s, m);
+  const WaveCell wf = wave_cell(lane_f(ends, 0), s, m), wl = wave_cell(lane_f(ends, 1), s, m);
   if (!uni(wf.ok && wl.ok ? 1 : 0)) return false;
   const int j0f = uni(wf.j0), j0l = uni(wl.j0);
   const int ncell = j0l - j0f + 1;
@@ -443,12 +470,15 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   //     first point of every cell, kf[q] (cell j0f + q): a point whose cell is
   //     above the previous point's starts the cells in between.  The previous
   //     point's cell comes from the lane below, or for lane 0 from the last
-  //     point of the previous pass.
+  //     point of the previous pass.  Each pass requests the next pass's points
+  //     before it works on its own.
   int carry = j0f - 1;
   for (int k0 = 0; k0 < np; k0 += WAVE) {
     const int k = k0 + lane;
-    int j0 = j0l;
-    if (k < np) j0 = point_setup<MODE>(m, s, c, pts[k], k, L);
+    const float2 nxt = k + WAVE < np ? pts[k + WAVE] : make_float2(0.f, 0.f);
+    int j0 = point_setup<MODE>(m, s, c, clq, cur, k, np, L);
+    if (k >= np) j0 = j0l;
+    cur = nxt;
     int prev = __shfl_up(j0, 1, WAVE);
     if (lane == 0) prev = carry;
     if (k < np)
