@@ -120,6 +120,42 @@ def test_small_batch_every_result(ctx6, o6, torch):
     assert flux_rel_err(f_fwd, f64, b.sn_offsets).max() <= FLUX_TOL
 
 
+def test_adjoint_vs_central_differences(ctx6, torch):
+    """The adjoint's Jacobian rows against central differences of the GPU forward kernel, step
+    h_q = 1e-4 max(|theta_q|, s_q) with s = (0.1, 1 d, x0, 1, 0.1).  Both sides run in FP32: the
+    forward kernel's rounding (about 1e-7 of f, 2.1e-7 at most against FP64) divided by the step
+    puts the differences within about 1e-3 of the row's scale |x0 df/dx0| = |f|, so each
+    observation's scaled row is held norm-wise to 1e-2 (the FP64 differences that pin the
+    oracle's own gradient are a CPU test)."""
+    model = synth.make_model()
+    b = synth.random_batch(47, 64, 5, 120, synth.make_bands(6), model)
+    f, J, _ = run_jac(ctx6, b, torch)
+    P = np.stack([b.z, b.t0, b.x0, b.x1, b.c], axis=1).astype(np.float64)
+    scale = np.stack([np.full(b.n_sn, 0.1), np.ones(b.n_sn), b.x0.astype(np.float64),
+                      np.ones(b.n_sn), np.full(b.n_sn, 0.1)], axis=1)
+    d = to_dev(b, torch)
+    n_s = np.diff(b.sn_offsets)
+    J_fd = np.zeros_like(J, dtype=np.float64)
+    for q, name in enumerate(("z", "t0", "x0", "x1", "c")):
+        h = 1e-4 * np.maximum(np.abs(P[:, q]), scale[:, q])
+        vals = []
+        for sign in (1.0, -1.0):
+            v = np.float32(P[:, q] + sign * h)
+            dd = dict(d)
+            dd[name] = torch.from_numpy(v).cuda()
+            vals.append(ctx6.bandflux(**dd).cpu().numpy().astype(np.float64))
+            hq = (np.float64(np.float32(P[:, q] + h)) - np.float64(np.float32(P[:, q] - h)))  # steps as rounded
+        J_fd[:, q] = (vals[0] - vals[1]) / np.repeat(hq, n_s)
+    ctx6.device_check()
+    s_obs = np.repeat(scale, n_s, axis=0)
+    Jt, Jt_fd = J.astype(np.float64) * s_obs, J_fd * s_obs
+    row = np.max(np.abs(Jt), axis=1)
+    live = row > 0
+    err = np.max(np.abs(Jt_fd - Jt), axis=1)[live] / row[live]
+    print(f"adjoint vs central differences: scaled row error max {err.max():.3e} median {np.median(err):.3e}")
+    assert err.max() <= 1e-2
+
+
 # ----------------------------------------------------------------------------- the 4,096-supernova batch
 
 def sample_sns(batch, n=40, seed=3):
