@@ -306,27 +306,26 @@ __device__ inline void tail_cols(float (&acc)[4][4], const typename ModeInfo<MOD
 }
 
 // One window column j of the adjoint's row projections from the lane's row
-// nodes cur = (M0, M1)(j), with the previous column's nodes prev and difference
-// weight gdp: the first difference D(j-1) = M(j) - M(j-1) is formed here (one
-// FP32 subtraction per surface, as exact as a stored difference) and its term
-// goes to the previous column's chain, after that column's own terms, so every
-// chain sums in column order.  Chains are window columns mod 4 (U = this one's).
+// nodes cur = (M0, M1)(j), with the previous column's combined node prev =
+// (M0 + x1 M1)(j-1) and difference weight gdp: the first difference of the
+// combined nodes, mx(j) - mx(j-1), is formed here and its term goes to the
+// previous column's chain, after that column's own terms, so every chain sums
+// in column order.  Chains are window columns mod 4 (U = this one's).
 template <int U>
-__device__ inline void col_step_d(float (&acc)[4][4], float4 g, float2 cur, float2& prev, float& gdp, float x1) {
+__device__ inline void col_step_d(float (&acc)[4][4], float4 g, float2 cur, float& prev, float& gdp, float x1) {
   constexpr int P = (U + 3) & 3;
-  const float dx = fmaf(x1, cur.y - prev.y, cur.x - prev.x);
-  acc[P][3] = fmaf(gdp, dx, acc[P][3]);
   const float mx = fmaf(x1, cur.y, cur.x);
+  acc[P][3] = fmaf(gdp, mx - prev, acc[P][3]);
   acc[U][0] = fmaf(g.x, mx, acc[U][0]);
   acc[U][1] = fmaf(g.x, cur.y, acc[U][1]);
   acc[U][2] = fmaf(g.y, mx, acc[U][2]);
   acc[U][3] = fmaf(g.z, mx, acc[U][3]);
-  prev = cur;
+  prev = mx;
   gdp = g.w;
 }
 
 template <int CW>
-__device__ inline void chunk_cols_d(float (&acc)[4][4], const float4* g, const float2 (&v)[CW], float2& prev,
+__device__ inline void chunk_cols_d(float (&acc)[4][4], const float4* g, const float2 (&v)[CW], float& prev,
                                     float& gdp, float x1) {
   static_assert(CW == 4, "one chunk is one column per chain");
   col_step_d<0>(acc, g[0], v[0], prev, gdp, x1);
@@ -335,19 +334,18 @@ __device__ inline void chunk_cols_d(float (&acc)[4][4], const float4* g, const f
   col_step_d<3>(acc, g[3], v[3], prev, gdp, x1);
 }
 
-// The difference term of the window's last column, on chain P, from the column
-// after the window, nx.  Its weight is zero; the term is kept so that every chain
+// The difference term of the window's last column, on chain P, from the nodes
+// of the column after the window, nx.  Its weight is zero; the term is kept so that every chain
 // ends as the column loop leaves it.
 template <int P>
-__device__ inline void close_chain(float (&acc)[4][4], float2 nx, float2 prev, float gdp, float x1) {
-  const float dx = fmaf(x1, nx.y - prev.y, nx.x - prev.x);
-  acc[P][3] = fmaf(gdp, dx, acc[P][3]);
+__device__ inline void close_chain(float (&acc)[4][4], float2 nx, float prev, float gdp, float x1) {
+  acc[P][3] = fmaf(gdp, fmaf(x1, nx.y, nx.x) - prev, acc[P][3]);
 }
 
 // The last rem (< 4) window columns, held in v[0 .. rem-1], and the closing
 // difference term from v[rem] (branches on the uniform rem, static indices only).
 __device__ inline void tail_cols_d(float (&acc)[4][4], const float4* g, const float2 (&v)[4], int rem,
-                                   float2& prev, float& gdp, float x1) {
+                                   float& prev, float& gdp, float x1) {
   if (rem == 0) {
     close_chain<3>(acc, v[0], prev, gdp, x1);
     return;
@@ -426,11 +424,12 @@ __device__ inline int point_setup(const KModel& m, double s, float c, float2 clq
 //   r=1  sum_j G(j)  M1[a, j]                          (FIT, VJP)
 //   r=2  sum_j Gc(j) (M0 + x1 M1)[a, j]                (FIT, VJP)
 //   r=3  sum_j Glc(j) (M0 + x1 M1)[a, j]
-//        + sum_j Gd(j) (D0 + x1 D1)[a, j]              (VJP)
+//        + sum_j Gd(j) D[a, j]                         (VJP)
 // with om_k = W_k exp(c CL(mu_k)) and
 //   G(j)   = sum_k om_k wl_j(mu_k),          Gc(j) = sum_k om_k CL(mu_k) wl_j(mu_k),
 //   Glc(j) = sum_k om_k mu_k c CL'(mu_k) wl_j(mu_k),
-//   Gd(j)  = sum_k om_k mu_k e_j(mu_k) / dwave   (difference weights, D(j) = M(j+1) - M(j)),
+//   Gd(j)  = sum_k om_k mu_k e_j(mu_k) / dwave   (difference weights on the first
+//            differences D(j) = (M0 + x1 M1)(j+1) - (M0 + x1 M1)(j) of the combined nodes),
 // so that r=3 gives sum_k om_k mu_k [dI/dmu + c CL' I] at the phase rows.
 // Every lane of one wave calls it, with that wave's scratch in L; it
 // synchronises only within the wave.  Returns false, uniformly, when the band's
@@ -519,7 +518,7 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   const int nrow = rhi - rlo + 1;
   if constexpr (MODE == VJP) {
     // the adjoint reads the node surface like the other modes and forms the
-    // first differences on the way (see col_step_d)
+    // first differences of the combined nodes on the way (see col_step_d)
     const int cstride = m.row_pad * (int)sizeof(float2);
     const int n4 = J >> 2, rem = J & 3;
     const __amdgpu_buffer_rsrc_t rs =
@@ -533,7 +532,7 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[u][r] = 0.f;
-      float2 prev = make_float2(0.f, 0.f);
+      float prev = 0.f;
       float gdp = 0.f;
       float2 A[4], B[4];
       load_cols<4>(A, rs, loff, cb, cstride);
