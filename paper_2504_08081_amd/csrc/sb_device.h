@@ -228,11 +228,13 @@ template <> __device__ inline float4 vzero<float4>() { return make_float4(0.f, 0
 // Tap sums of one wavelength cell over its points k in [k0, k1):
 //   C[t] = sum_k wl_t(x_k) P_k      (node tap t lands on column cell - 1 + t)
 // and, for the adjoint's difference weights (component w), C[t].w = sum_k
-// e_t(x_k) P_k.w for t < 3 (difference D(cell - 1 + t)).
-template <int MODE>
-__device__ inline void cell_taps(typename ModeInfo<MODE>::V (&C)[4], const Lds& L, int k0, int k1, bool edge) {
+// e_t(x_k) P_k.w for t < 3 (difference D(cell - 1 + t)).  MAY_EDGE false: the
+// caller knows that the cell is not a first or last cell of the grid.
+template <int MODE, bool MAY_EDGE>
+__device__ inline void cell_taps(typename ModeInfo<MODE>::V (&C)[4], const Lds& L, int k0, int k1, bool edge_in) {
   typedef typename ModeInfo<MODE>::V V;
   const V* Pv = (const V*)L.P;
+  const bool edge = MAY_EDGE && edge_in;
   for (int k = k0; k < k1; ++k) {
     const float x = L.x[k];
     const V p = Pv[k];
@@ -494,14 +496,20 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   //     that one, held by lane L - t: G = C0 + up(C1 + up(C2 + up(C3))).
   //     Passes start 3 columns early and advance by WAVE - 3, so every tap a
   //     written column needs comes from a lane of the same pass.
+  //     Only a window that reaches the grid's first or last cell can hold an
+  //     edge cell, so other windows take the branch without the edge weights.
+  const bool win_edge = uni(j0f == 0 || j0l >= m.n_wave - 2 ? 1 : 0);
   for (int b = -3; b + 3 < J; b += WAVE - 3) {
     const int col = b + lane;
     const int cell = j_lo + col + 1;
     const int q = cell - j0f;
     V C[4] = {vzero<V>(), vzero<V>(), vzero<V>(), vzero<V>()};
     if (q >= 0 && q < ncell) {
-      const bool edge = (cell == 0) || (cell == m.n_wave - 2);
-      cell_taps<MODE>(C, L, max(L.kf[q], 0), min(L.kf[q + 1], np), edge);
+      const int k0 = max(L.kf[q], 0), k1 = min(L.kf[q + 1], np);
+      if (win_edge)
+        cell_taps<MODE, true>(C, L, k0, k1, (cell == 0) || (cell == m.n_wave - 2));
+      else
+        cell_taps<MODE, false>(C, L, k0, k1, false);
     }
     V g = C[2] + up1(C[3]);
     g = C[1] + up1(g);
