@@ -21,7 +21,7 @@ struct SnShared {
   int rhi[SB_MAX_BANDS];
   int slot_of[SB_MAX_BANDS];   // band -> its slot in the current group, -1 otherwise
   int slot_ok[BAND_GROUP];
-  float red[MAX_NW * 8];
+  float red[red_floats(8, MAX_NW)];
 };
 
 // Per-observation outputs of an observation that cannot be evaluated.

@@ -654,31 +654,55 @@ __device__ inline void take_group(unsigned& rem0, unsigned& rem1, unsigned& g0, 
   }
 }
 
+// Sum over the 64 lanes of a wave; every lane receives the same value.  A
+// butterfly in ascending distance: distances 1 and 2 are quad permutes, and 4
+// and 8 are the row half-mirror and mirror, which pair a lane with a partner
+// holding the same partial sum as its xor partner (after the shorter distances
+// every lane of a 4- or 8-lane group holds the same bits, float addition being
+// commutative); 16 and 32 cross rows through the LDS permute unit.
+template <int CTRL>
+__device__ inline float dpp_mov(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+__device__ inline float wave_sum(float x) {
+  x += dpp_mov<0xB1>(x);    // quad_perm [1,0,3,2]: lane ^ 1
+  x += dpp_mov<0x4E>(x);    // quad_perm [2,3,0,1]: lane ^ 2
+  x += dpp_mov<0x141>(x);   // row_half_mirror: 7 - lane within 8 (same sum as lane ^ 4)
+  x += dpp_mov<0x140>(x);   // row_mirror: 15 - lane within 16 (same sum as lane ^ 8)
+  x += __shfl_xor(x, 16, WAVE);
+  x += __shfl_xor(x, 32, WAVE);
+  return x;
+}
+
+// Floats of the reduction scratch block_sum<N, NW> needs: the waves'
+// partials and the result, each padded to a multiple of 4.
+constexpr int red_pad(int n) { return (n + 3) & ~3; }
+constexpr int red_floats(int n, int nw) { return (nw + 1) * red_pad(n); }
+
 // Sum of N values over a workgroup of NW waves in a fixed order; every thread
-// gets the same result (each thread adds the per-wave partials in wave order).
+// gets the same result.  Each wave sums its lanes (wave_sum), lane 0 stores the
+// wave's partials, thread q < N adds them in wave order, and every thread reads
+// the N sums.  red holds red_floats(N, NW) floats.
 template <int N, int NW>
 __device__ inline void block_sum(float (&v)[N], float* red) {
+  constexpr int NP = red_pad(N);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 #pragma unroll
-  for (int q = 0; q < N; ++q) {
-    float x = v[q];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    v[q] = x;
-  }
+  for (int q = 0; q < N; ++q) v[q] = wave_sum(v[q]);
   if (lane == 0) {
 #pragma unroll
-    for (int q = 0; q < N; ++q) red[wv * N + q] = v[q];
+    for (int q = 0; q < N; ++q) red[wv * NP + q] = v[q];
+  }
+  __syncthreads();
+  if (tid < N) {
+    float x = red[tid];
+#pragma unroll
+    for (int w2 = 1; w2 < NW; ++w2) x += red[w2 * NP + tid];
+    red[NW * NP + tid] = x;
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < N; ++q) {
-    float x = red[q];
-#pragma unroll
-    for (int w2 = 1; w2 < NW; ++w2) x += red[w2 * N + q];
-    v[q] = x;
-  }
-  __syncthreads();
+  for (int q = 0; q < N; ++q) v[q] = red[NW * NP + q];
 }
 
 // Branch-free reset of the per-band scan state (every thread stores the same

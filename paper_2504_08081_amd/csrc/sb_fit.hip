@@ -23,7 +23,7 @@ struct FitShared {
   int rhi[SB_MAX_BANDS];
   int slot_of[SB_MAX_BANDS];
   int slot_ok[BAND_GROUP];
-  float red[MAX_NW * 16];
+  float red[red_floats(16, MAX_NW)];
 };
 
 // chi2, H (packed) and g at parameters q = (t0, ln x0, x1, c); every thread gets them.
