@@ -148,29 +148,42 @@ __device__ bool damped_solve(const float* H, const float* g, float lambda, int f
     if (fr) a[i][i] = fmaf(lambda, a[i][i], a[i][i]);
     rhs[i] = fr ? g[i] : 0.f;
   }
+  // L L^T with the pivots' reciprocal square roots kept (inv[i] = 1 / L_ii), so
+  // every division is a multiplication: the step is a descent direction whose
+  // trial point is evaluated before it is accepted, so the hardware reciprocal
+  // square root's last-bit error is harmless
   float l[4][4] = {};
+  float inv[4];
+#pragma unroll
   for (int i = 0; i < 4; ++i) {
+#pragma unroll
     for (int j = 0; j <= i; ++j) {
       float sum = a[i][j];
-      for (int p = 0; p < j; ++p) sum -= l[i][p] * l[j][p];
+#pragma unroll
+      for (int p = 0; p < j; ++p) sum = fmaf(-l[i][p], l[j][p], sum);
       if (i == j) {
         if (!(sum > 0.f) || !isfinite(sum)) return false;
-        l[i][i] = sqrtf(sum);
+        inv[i] = __builtin_amdgcn_rsqf(sum);
+        l[i][i] = sum * inv[i];
       } else {
-        l[i][j] = sum / l[j][j];
+        l[i][j] = sum * inv[j];
       }
     }
   }
   float y[4];
+#pragma unroll
   for (int i = 0; i < 4; ++i) {
     float sum = rhs[i];
-    for (int p = 0; p < i; ++p) sum -= l[i][p] * y[p];
-    y[i] = sum / l[i][i];
+#pragma unroll
+    for (int p = 0; p < i; ++p) sum = fmaf(-l[i][p], y[p], sum);
+    y[i] = sum * inv[i];
   }
+#pragma unroll
   for (int i = 3; i >= 0; --i) {
     float sum = y[i];
-    for (int p = i + 1; p < 4; ++p) sum -= l[p][i] * d[p];
-    d[i] = sum / l[i][i];
+#pragma unroll
+    for (int p = i + 1; p < 4; ++p) sum = fmaf(-l[p][i], d[p], sum);
+    d[i] = sum * inv[i];
   }
   for (int i = 0; i < 4; ++i)
     if (!isfinite(d[i])) return false;
