@@ -250,4 +250,9 @@ def test_poll_and_ticket_lifecycle(sb, model, bands6, requests):
     with pytest.raises(sb.SaltBFError) as e:
         ctx.fit_poll(tk)          # a result is handed out once
     assert e.value.status == sb.SB_ERR_NOTFOUND
+    # one fit of 50 iterations at 5 per launch: ten launches with one fit each
+    st = ctx.stats()
+    assert st["submitted"] == st["admitted"] == st["completed"] == 1
+    assert st["ticks"] == 10 and st["slot_ticks"] == 10
+    assert st["active_slots"] == 0 and st["queue_depth"] == 0 and st["bytes_in_use"] == 0
     ctx.close()
