@@ -181,6 +181,7 @@ struct Lds {
   void* P;     // [max_pts] of V             weight factors per quadrature point
   float* x;    // [max_pts]                  fraction in the point's wavelength cell
   int* kf;     // [jcap + 2]                 first point of each cell
+  int* tag;    // [4] after kf               fit mode: band held in P, x, kf (-1: none), j0f, j0l, np
   void* G;     // [jcap] of V                weight vectors over the window
   float* R;    // [GROUP][n_phase][NR]       row projections of the bands of a group
 };
@@ -192,7 +193,7 @@ __host__ __device__ inline size_t wave_scratch_bytes(int max_pts, int jcap) {
   size_t b = 0;
   b += (size_t)max_pts * sizeof(V);
   b += (size_t)max_pts * sizeof(float);
-  b += (size_t)(jcap + 2) * sizeof(int);
+  b += (size_t)(jcap + 2 + 4) * sizeof(int);
   b = (b + 15) & ~(size_t)15;
   b += (size_t)jcap * sizeof(V);
   return (b + 15) & ~(size_t)15;
@@ -214,6 +215,7 @@ __device__ inline Lds lds_carve(char* base, const KModel& m, const KTables& tb, 
   L.P = base + o;            o += (size_t)tb.max_pts * sizeof(V);
   L.x = (float*)(base + o);  o += (size_t)tb.max_pts * sizeof(float);
   L.kf = (int*)(base + o);   o += (size_t)(tb.jcap + 2) * sizeof(int);
+  L.tag = (int*)(base + o);  o += 4 * sizeof(int);
   o = (o + 15) & ~(size_t)15;
   L.G = base + o;
   L.R = (float*)(base + (size_t)NW * ws);
@@ -231,13 +233,19 @@ template <> __device__ inline float4 vzero<float4>() { return make_float4(0.f, 0
 // e_t(x_k) P_k.w for t < 3 (difference D(cell - 1 + t)).  MAY_EDGE false: the
 // caller knows that the cell is not a first or last cell of the grid.
 template <int MODE, bool MAY_EDGE>
-__device__ inline void cell_taps(typename ModeInfo<MODE>::V (&C)[4], const Lds& L, int k0, int k1, bool edge_in) {
+__device__ inline void cell_taps(typename ModeInfo<MODE>::V (&C)[4], const Lds& L, int k0, int k1, bool edge_in,
+                                 float c) {
   typedef typename ModeInfo<MODE>::V V;
   const V* Pv = (const V*)L.P;
   const bool edge = MAY_EDGE && edge_in;
   for (int k = k0; k < k1; ++k) {
     const float x = L.x[k];
-    const V p = Pv[k];
+    V p = Pv[k];
+    if constexpr (MODE == FIT) {
+      // the fit keeps (W_k, CL(mu_k)), which depend on z only; om_k follows the colour
+      const float om = p.x * expf(c * p.y);
+      p = make_float2(om, om * p.y);
+    }
     float w[4];
     cr_weights(x, edge, w);
 #pragma unroll
@@ -404,14 +412,20 @@ __device__ inline int point_setup(const KModel& m, double s, float c, float2 clq
   const WaveCell w = wave_cell(lw.x, s, m);
   float cl, dcl;
   colour_law(w.mu, m, clq, cl, dcl);
+  if constexpr (MODE == FIT) {
+    // the colour factor is applied in the weight pass (cell_taps)
+    if (k < np) {
+      ((V*)L.P)[k] = make_float2(lw.y, cl);
+      L.x[k] = w.x;
+    }
+    return w.j0;
+  }
   const float om = lw.y * expf(c * cl);
   if (k < np) {
     V* Pv = (V*)L.P;
     if constexpr (MODE == FWD) {
       Pv[k] = om;
-    } else if constexpr (MODE == FIT) {
-      Pv[k] = make_float2(om, om * cl);
-    } else {
+    } else if constexpr (MODE == VJP) {
       const float omu = om * w.mu;
       Pv[k] = make_float4(om, om * cl, omu * (c * dcl), omu * m.inv_dwave);
     }
@@ -443,24 +457,36 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   typedef typename ModeInfo<MODE>::V V;
   constexpr int NR = ModeInfo<MODE>::NR;
   const int lane = threadIdx.x & (WAVE - 1);
-  const int np = uni(tb.npts[bd]);
   bd = uni(bd);
   rlo = uni(rlo);
   rhi = uni(rhi);
-  const float2* pts = tb.pts + (size_t)bd * SB_MAX_BAND_POINTS;
   V* Gv = (V*)L.G;
 
-  // the first pass's points, and the band's first and last point (lanes 0 and
-  // 1 of one load), are requested before anything waits on memory
-  float2 cur = lane < np ? pts[lane] : make_float2(0.f, 0.f);
-  const float ends = pts[lane == 0 ? 0 : np - 1].x;
-  const float2 clq = colour_coefs(m);
-
-  // the window: the cells of the first and last points (cells are non-decreasing
-  // in k, so every point is on the grid if these two are)
-  const WaveCell wf = wave_cell(lane_f(ends, 0), s, m), wl = wave_cell(lane_f(ends, 1), s, m);
-  if (!uni(wf.ok && wl.ok ? 1 : 0)) return false;
-  const int j0f = uni(wf.j0), j0l = uni(wl.j0);
+  // A fit evaluates the same bands at the same redshift in every iteration: the
+  // points' cells, fractions, colour law and the cell table depend on z only, so
+  // a wave whose scratch already holds this band (tag) goes straight to (3).
+  bool cached = false;
+  if constexpr (MODE == FIT) cached = uni(L.tag[0] == bd ? 1 : 0) != 0;
+  int np, j0f, j0l;
+  float2 cur = make_float2(0.f, 0.f);
+  const float2* pts = tb.pts + (size_t)bd * SB_MAX_BAND_POINTS;
+  if (cached) {
+    j0f = uni(L.tag[1]);
+    j0l = uni(L.tag[2]);
+    np = uni(L.tag[3]);
+  } else {
+    np = uni(tb.npts[bd]);
+    // the first pass's points, and the band's first and last point (lanes 0 and
+    // 1 of one load), are requested before anything waits on memory
+    cur = lane < np ? pts[lane] : make_float2(0.f, 0.f);
+    const float ends = pts[lane == 0 ? 0 : np - 1].x;
+    // the window: the cells of the first and last points (cells are non-decreasing
+    // in k, so every point is on the grid if these two are)
+    const WaveCell wf = wave_cell(lane_f(ends, 0), s, m), wl = wave_cell(lane_f(ends, 1), s, m);
+    if (!uni(wf.ok && wl.ok ? 1 : 0)) return false;
+    j0f = uni(wf.j0);
+    j0l = uni(wl.j0);
+  }
   const int ncell = j0l - j0f + 1;
   const int j_lo = j0f - 1 < 0 ? 0 : j0f - 1;
   const int j_hi = j0l + 2 > m.n_wave - 1 ? m.n_wave - 1 : j0l + 2;
@@ -473,6 +499,8 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   //     point's cell comes from the lane below, or for lane 0 from the last
   //     point of the previous pass.  Each pass requests the next pass's points
   //     before it works on its own.
+  if (!cached) {
+  const float2 clq = colour_coefs(m);
   int carry = j0f - 1;
   for (int k0 = 0; k0 < np; k0 += WAVE) {
     const int k = k0 + lane;
@@ -486,7 +514,16 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
       for (int q = prev + 1; q <= j0; ++q) L.kf[q - j0f] = k;
     carry = __builtin_amdgcn_readlane(j0, min(np - k0, WAVE) - 1);
   }
-  if (lane == 0) L.kf[ncell] = np;
+  if (lane == 0) {
+    L.kf[ncell] = np;
+    if (MODE == FIT) {
+      L.tag[0] = bd;
+      L.tag[1] = j0f;
+      L.tag[2] = j0l;
+      L.tag[3] = np;
+    }
+  }
+  }
   wave_sync();
 
   // (3) weight vectors over the window of columns [j_lo, j_hi].  Lane L of a
@@ -507,9 +544,9 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
     if (q >= 0 && q < ncell) {
       const int k0 = max(L.kf[q], 0), k1 = min(L.kf[q + 1], np);
       if (win_edge)
-        cell_taps<MODE, true>(C, L, k0, k1, (cell == 0) || (cell == m.n_wave - 2));
+        cell_taps<MODE, true>(C, L, k0, k1, (cell == 0) || (cell == m.n_wave - 2), c);
       else
-        cell_taps<MODE, false>(C, L, k0, k1, false);
+        cell_taps<MODE, false>(C, L, k0, k1, false, c);
     }
     V g = C[2] + up1(C[3]);
     g = C[1] + up1(g);

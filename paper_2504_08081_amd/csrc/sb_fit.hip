@@ -196,6 +196,8 @@ __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F)
   extern __shared__ __align__(16) char smem[];
   __shared__ FitShared S;
   const Lds L = lds_carve<FIT, NW>(smem, m, tb, uni((int)(threadIdx.x / WAVE)));
+  // no band's point data in this launch's scratch yet (read after the first barrier)
+  if ((threadIdx.x & (WAVE - 1)) == 0) L.tag[0] = -1;
   const int tid = threadIdx.x;
   FitSlot* sl = F.slots + F.active[blockIdx.x];
   const int adm = uni(F.admit[blockIdx.x]);
