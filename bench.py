@@ -198,16 +198,25 @@ def cpu_baseline_isolated(batch, model, bands, budget_s):
 PROFILE_VJP = os.path.join(ROOT, "profiles", "k_sn_vjp_4096sn.md")
 
 
+def code_only(text):
+    """C/C++ source without comments, trailing spaces and blank lines."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+
+
 def kernel_sources_sha256():
-    """Hash of the device sources (kernels and the headers they include)."""
+    """Hash of the device sources' code (kernels and the headers they include; comments do not
+    count, so a profile stays valid across comment edits)."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2504_08081_amd", "csrc")
     for f in sorted(os.listdir(d)):
         if f.endswith((".hip", ".h")):
             h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+            with open(os.path.join(d, f), encoding="utf-8") as fh:
+                h.update(code_only(fh.read()).encode())
     return h.hexdigest()
 
 

@@ -401,7 +401,8 @@ __device__ inline WaveCell wave_cell(float lam, double s, const KModel& m) {
 
 // Quadrature point k of a band, (lam_k, W_k) = lw, for a supernova with
 // s = 1/(1+z) and colour c: its fraction x and weight factors P (om_k = W_k
-// exp(c CL(mu_k)), and per mode om_k CL, om_k mu_k c CL', om_k mu_k / dwave)
+// exp(c CL(mu_k)), and per mode om_k CL, om_k mu_k c CL', om_k mu_k / dwave;
+// the fit stores (W_k, CL(mu_k)) and applies the colour in the weight pass)
 // into the wave's scratch, if k < np.  Every lane of the wave calls it (the
 // colour law reads its coefficients across lanes).  Returns the point's
 // wavelength cell.
