@@ -353,6 +353,17 @@ def test_results_do_not_depend_on_the_rest_of_the_batch(ctx6, big_batch, torch):
     ctx6.device_check()
 
 
+def test_few_supernova_forward_matches_the_batch_kernel(ctx6, big_batch, torch):
+    """Forward calls on at most 64 supernovae run one wave per band; their fluxes are bitwise those
+    of the same supernovae in the 4,096-supernova batch."""
+    full = ctx6.bandflux(**to_dev(big_batch, torch)).cpu()
+    for idx in (np.array([7]), np.arange(100, 110), np.arange(4032, 4096)):
+        sel = np.concatenate([np.arange(big_batch.sn_offsets[i], big_batch.sn_offsets[i + 1]) for i in idx])
+        part = ctx6.bandflux(**to_dev(big_batch.subset(idx), torch)).cpu()
+        assert torch.equal(part, full[torch.from_numpy(sel)]), len(idx)
+    ctx6.device_check()
+
+
 # ----------------------------------------------------------------------------- autograd
 
 def test_autograd_function(ctx6, torch):
