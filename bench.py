@@ -413,6 +413,7 @@ def main():
         chi_pl = torch.empty(n, device="cuda")
         d_pl, wall_pl = time_launches(torch, ctx.prepare_bandflux(**P, t=tt, band=bb, sn_offsets=off, chi2=True,
                                                                   data=dd, inv_sigma2=ww, out=chi_pl), reps, 1)
+        ctx.device_check()
         same = bool(torch.equal(chi, chi_pl))
         del tt, bb, off, dd, ww
         evals = n * no
@@ -430,6 +431,7 @@ def main():
         Db["data"], Db["inv_sigma2"] = dv(bd), dv(bw)
         gb = torch.empty((big.n_sn, 5), device="cuda")
         d_b, wall_b = time_launches(torch, ctx.prepare_bandflux_vjp(**Db, chi2=True, grad=gb), 10, 2)
+        ctx.device_check()   # every band window of the batch was on the grid
         result["big_fwd_adj"] = {"n_sn": big.n_sn, "n_obs": big.n_obs, "kernel_ms": float(d_b.mean()),
                                  "evals_per_s": big.n_obs * 10 / wall_b}
         log(f"big: {result['big_fwd_adj']}")

@@ -35,9 +35,11 @@ WAVE0, DWAVE, NWAVE = 2000.0, 10.0, 721
 CL_WAVE_B, CL_WAVE_V = 4302.57, 5428.55
 # Quadrature spacing bound of the observer-frame grid (Angstrom).
 MAX_SPACING = 5.0
-# Keep a band's rest-frame window this far (Angstrom) inside the surface grid
-# so that float32 and float64 agree on eligibility.
-ELIG_MARGIN = 2.0
+# Keep a band's rest-frame window this far (Angstrom) inside the surface grid,
+# so that float32 and float64 agree on eligibility and the redshift steps of
+# perturb() (|dz| <= 3e-3, which move the window's blue end by at most 3.5 A
+# where a band can reach the grid's edge) keep every window on the grid.
+ELIG_MARGIN = 6.0
 
 
 def rng(k: int) -> np.random.Generator:

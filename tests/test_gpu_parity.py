@@ -216,6 +216,32 @@ def test_batch_4096_chi2_gradient_sampled(ctx6, o6, big_batch, torch):
     assert ef.max() <= FLUX_TOL
 
 
+def test_batch_65536_forward_adjoint_sampled(ctx6, o6, torch):
+    """The 65,536 x 100 batch, forward + adjoint with random cotangents on the GPU in one launch:
+    sampled supernovae's fluxes and gradients against the oracle (flux 1e-5; gradient norm-wise
+    1e-4, each component to 1e-4 or its FP32 conditioning bound, as for the small batch)."""
+    print("case: 65536-SN forward + adjoint", flush=True)
+    b = synth.perturb(synth.batch_65536_sn(), k=7)
+    cot = np.random.default_rng(23).normal(size=b.n_obs).astype(np.float32)
+    r = ctx6.bandflux_vjp(**to_dev(b, torch), cotangent=torch.from_numpy(cot).cuda(), want_flux=True)
+    ctx6.device_check()
+    idx = sample_sns(b, n=24, seed=9)
+    sub = b.subset(idx)
+    sel = np.concatenate([np.arange(b.sn_offsets[s], b.sn_offsets[s + 1]) for s in idx])
+    f64, J64 = o6.jac(sub)
+    g64 = oracle.segment_sum(cot[sel].astype(np.float64)[:, None] * J64, sub.sn_offsets)
+    f = r["flux"].cpu().numpy()[sel]
+    grad = r["grad"].cpu().numpy()[idx]
+    ef = flux_rel_err(f, f64, sub.sn_offsets)
+    en = grad_norm_err(grad, g64, sub.x0)
+    eg = grad_rel_err(grad, g64, sub.x0)
+    ec = grad_cond_excess(grad, g64, sub.x0, cot[sel], J64, sub.sn_offsets)
+    print(f"65536-SN sampled {len(idx)} SN: flux {ef.max():.3e} grad norm-wise {en.max():.3e} "
+          f"component-wise {eg.max():.3e}")
+    assert ef.max() <= FLUX_TOL and en.max() <= GRAD_TOL
+    assert np.all((eg <= GRAD_TOL) | (ec <= 1.0))
+
+
 def test_run_twice_bitwise(ctx6, big_batch, torch):
     d = to_dev(big_batch, torch)
     cot = torch.ones(big_batch.n_obs, dtype=torch.float32, device="cuda")
