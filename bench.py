@@ -262,7 +262,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--sweep-samples", type=int, default=1 << 20)
     ap.add_argument("--legs", default="one,fwd,sweep,big,serve")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -481,7 +481,7 @@ def serve_leg(torch, saltbf, model, bands, seconds, **config):
     """Poisson arrivals at 2,000 req/s: submit each request at its arrival time, collect p50/p99.
     config: sb_config overrides for the serving context."""
     rate = 2000.0
-    n_req = int(rate * (seconds + 0.5))
+    n_req = int(rate * (seconds + 1.0))   # a 1 s warm-up, then the measured seconds
     reqs = synth.fit_requests(n_req, rate=rate)
     ctx = saltbf.Context.from_model(model, bands, **config)
     dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -512,7 +512,7 @@ def serve_leg(torch, saltbf, model, bands, seconds, **config):
     res = [ctx.fit_wait(tk, 30.0) for tk in tickets]
     stats = ctx.stats()
     ctx.close()
-    warm = int(0.5 * rate)
+    warm = int(1.0 * rate)
     lat = np.array([(x.t_done - x.t_submit) for x in res[warm:] if x is not None]) * 1e3
     queue = np.array([(x.t_admit - x.t_submit) for x in res[warm:] if x is not None]) * 1e3
     done = [x for x in res if x is not None]
