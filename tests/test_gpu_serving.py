@@ -67,10 +67,10 @@ def run_all(ctx, items, timeout=60.0):
 
 
 def test_fits_match_oracle(sb, o6, model, bands6, requests):
-    """Every GPU fit against the FP64 LM fit from the same start: parameters within 1e-2 of their
-    statistical uncertainty, chi2 within 1e-4."""
+    """Every GPU fit of 40 requests against the FP64 LM fit from the same start: parameters within
+    1e-2 of their statistical uncertainty, chi2 within 1e-4."""
     ctx = sb.Context.from_model(model, bands6)
-    items = requests[:12]
+    items = requests
     res = run_all(ctx, items)
     fo = oracle.FitOracle(o6)
     worst = 0.0
@@ -150,16 +150,22 @@ def test_fits_with_single_wave_workgroups(sb, o6, model, bands6, requests):
     ctx.close()
 
 
-def test_alone_vs_in_the_mix_bitwise(sb, model, bands6, requests):
-    """A fit alone and the same fit among 30 others sharing its launches give identical results."""
+def test_alone_vs_in_the_mix_bitwise(sb, o6, model, bands6):
+    """100 seeded requests: each fit run alone and the same fit among the other 99 sharing its
+    launches (all submitted at once) give identical results."""
+    items = []
+    for r in synth.fit_requests(100, k=45):
+        b = single_batch(r)
+        d, sig, w = synth.make_data(o6.bandflux(b), b.sn_offsets, r.normals)
+        items.append((r, d, sig, w))
     ctx = sb.Context.from_model(model, bands6)
-    probe = requests[5]
-    alone = run_all(ctx, [probe])[0]
-    mix_items = requests[10:25] + [probe] + requests[25:40]
-    mixed = run_all(ctx, mix_items)
-    assert result_key(mixed[15]) == result_key(alone)
+    alone = [run_all(ctx, [it])[0] for it in items]
+    mixed = run_all(ctx, items)
+    for i, (a, m) in enumerate(zip(alone, mixed)):
+        assert result_key(m) == result_key(a), i
     st = ctx.stats()
-    assert st["completed"] == 32 and st["queue_depth"] == 0 and st["active_slots"] == 0
+    assert st["completed"] == 200 and st["queue_depth"] == 0 and st["active_slots"] == 0
+    assert st["slot_ticks"] > st["ticks"]   # the mixed fits did share launches
     ctx.close()
 
 
