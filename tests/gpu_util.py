@@ -97,3 +97,64 @@ def grad_cond_excess(g_gpu, g64, x0, cot, J64, offsets, c=8.0):
         mag[s] = np.sum(np.abs(np.asarray(cot, np.float64)[lo:hi]) * row[lo:hi])
     err = np.abs((np.asarray(g_gpu, np.float64) - np.asarray(g64, np.float64)) * sc)
     return err / np.maximum(c * U32 * mag[:, None], 1e-300)
+
+
+def chi2_grad_propagated_excess(g_gpu, g64, x0, f64, data, w, J64, offsets, flux_tol=FLUX_TOL, c=8.0):
+    """Component error of a chi-square gradient over the error that fluxes within flux_tol propagate
+    into it: the cotangent 2 (f - d) w carries 2 w |delta f| <= 2 w flux_tol |f|, so component q
+    may be off by sum_i 2 w_i flux_tol |f_i| |J~_iq|, plus the FP32 arithmetic term of
+    grad_cond_excess.  Values <= 1 pass."""
+    sc = PARAM_SCALE[None, :] * np.ones((len(x0), 1))
+    sc[:, 2] = np.asarray(x0, np.float64)
+    n_s = np.diff(offsets)
+    Jt = np.abs(np.asarray(J64, np.float64) * np.repeat(sc, n_s, axis=0))
+    f = np.asarray(f64, np.float64)
+    ww = np.asarray(w, np.float64)
+    cot = 2.0 * (f - np.asarray(data, np.float64)) * ww
+    prop = np.zeros((len(x0), 5))
+    mag = np.zeros(len(x0))
+    for s in range(len(x0)):
+        lo, hi = int(offsets[s]), int(offsets[s + 1])
+        prop[s] = (2.0 * ww[lo:hi] * flux_tol * np.abs(f[lo:hi]))[:, None].T @ Jt[lo:hi]
+        mag[s] = np.sum(np.abs(cot[lo:hi]) * Jt[lo:hi].max(axis=1))
+    err = np.abs((np.asarray(g_gpu, np.float64) - np.asarray(g64, np.float64)) * sc)
+    return err / np.maximum(prop + c * U32 * mag[:, None], 1e-300)
+
+
+# ----------------------------------------------------------------------------- the oracle over a whole batch
+
+def _oracle_chunk(args):
+    """Worker: the oracle's fluxes, or chi-square and its gradient, for one chunk of supernovae."""
+    import oracle
+    import synth
+    kind, batch, data, w, n_bands = args
+    o = oracle.Oracle(synth.make_model(), synth.make_bands(n_bands))
+    if kind == "flux":
+        return o.bandflux(batch)
+    if kind == "jac":
+        return o.jac(batch)
+    return o.chi2_grad(batch, data, w)
+
+
+def oracle_over_batch(kind, batch, n_bands, data=None, w=None, workers=16, chunk=128):
+    """The FP64 oracle over every supernova of a batch, in chunks on a pool of CPU worker
+    processes (started with spawn, so they share nothing with the GPU process).
+    kind "flux": fluxes [n_obs]; kind "jac": (fluxes [n_obs], Jacobian rows [n_obs, 5]);
+    kind "chi2": (fluxes [n_obs], chi2 [n_sn], gradient [n_sn, 5])."""
+    import multiprocessing as mp
+    import os
+    jobs = []
+    for lo in range(0, batch.n_sn, chunk):
+        idx = np.arange(lo, min(batch.n_sn, lo + chunk))
+        sub = batch.subset(idx)
+        a, b = batch.sn_offsets[lo], batch.sn_offsets[idx[-1] + 1]
+        jobs.append((kind, sub, None if data is None else data[a:b], None if w is None else w[a:b], n_bands))
+    n = max(1, min(workers, os.cpu_count() or 1))
+    with mp.get_context("spawn").Pool(n) as pool:
+        out = pool.map(_oracle_chunk, jobs)
+    if kind == "flux":
+        return np.concatenate(out)
+    if kind == "jac":
+        return np.concatenate([o[0] for o in out]), np.concatenate([o[1] for o in out])
+    return (np.concatenate([o[0] for o in out]), np.concatenate([o[1] for o in out]),
+            np.concatenate([o[2] for o in out]))

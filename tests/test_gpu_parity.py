@@ -8,8 +8,8 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import (FLUX_TOL, GRAD_TOL, flux_rel_err, grad_cond_excess, grad_norm_err, grad_rel_err,
-                      jac_rel_err, to_dev, torch_or_skip)
+from gpu_util import (FLUX_TOL, GRAD_TOL, chi2_grad_propagated_excess, flux_rel_err, grad_cond_excess,
+                      grad_norm_err, grad_rel_err, jac_rel_err, oracle_over_batch, to_dev, torch_or_skip)
 
 pytestmark = pytest.mark.gpu
 
@@ -240,6 +240,42 @@ def test_batch_65536_forward_adjoint_sampled(ctx6, o6, torch):
           f"component-wise {eg.max():.3e}")
     assert ef.max() <= FLUX_TOL and en.max() <= GRAD_TOL
     assert np.all((eg <= GRAD_TOL) | (ec <= 1.0))
+
+
+def test_batch_4096_every_flux_chi2_and_gradient(ctx6, big_batch, torch):
+    """The whole 4,096-supernova batch against the oracle (run over all supernovae on a pool of
+    CPU processes): every flux at the true parameters, and every supernova's chi-square and
+    gradient at perturbed ones, data drawn around the oracle's true fluxes.  A gradient
+    component is a sum of terms of both signs (cotangent 2 (f - d) / sigma^2 times Jacobian
+    entries) that can cancel to far below its terms, and its cotangent is formed from a flux
+    whose own error |f - d| ~ 0.05 |f| magnifies twenty-fold; so besides the norm-wise 1e-4
+    bound each component is held to 1e-4 or to the error that fluxes within the 1e-5 flux
+    tolerance propagate into it."""
+    print("case: 4096-SN batch, every result", flush=True)
+    f_true64 = oracle_over_batch("flux", big_batch, 6)
+    f_gpu = ctx6.bandflux(**to_dev(big_batch, torch)).cpu().numpy()
+    ef = flux_rel_err(f_gpu, f_true64, big_batch.sn_offsets)
+    data, _, w = synth.make_data(f_true64, big_batch.sn_offsets, synth.noise_draws(big_batch.n_obs))
+    ev = synth.perturb(big_batch)
+    f64, c64, g64 = oracle_over_batch("chi2", ev, 6, data=data, w=w)
+    r = ctx6.bandflux_vjp(**to_dev(ev, torch), chi2=True, data=torch.from_numpy(data).cuda(),
+                          inv_sigma2=torch.from_numpy(w).cuda(), want_flux=True)
+    ctx6.device_check()
+    grad, chi2 = r["grad"].cpu().numpy(), r["chi2"].cpu().numpy()
+    ef2 = flux_rel_err(r["flux"].cpu().numpy(), f64, ev.sn_offsets)
+    eg = grad_rel_err(grad, g64, ev.x0)
+    en = grad_norm_err(grad, g64, ev.x0)
+    ec = np.abs(chi2 - c64) / np.abs(c64)
+    _, J64 = oracle_over_batch("jac", ev, 6)
+    ek = chi2_grad_propagated_excess(grad, g64, ev.x0, f64, data, w, J64, ev.sn_offsets)
+    print(f"4096-SN every result: flux {ef.max():.3e} (perturbed {ef2.max():.3e}), chi2 {ec.max():.3e}, "
+          f"grad component-wise {eg.max():.3e} (p99 {np.percentile(eg, 99):.3e}, "
+          f"{int(np.sum(eg > GRAD_TOL))} above 1e-4, worst over their propagated bound "
+          f"{ek[eg > GRAD_TOL].max() if np.any(eg > GRAD_TOL) else 0.0:.3f}), norm-wise {en.max():.3e}")
+    assert ef.max() <= FLUX_TOL and ef2.max() <= FLUX_TOL
+    assert ec.max() <= 1e-4
+    assert en.max() <= GRAD_TOL
+    assert np.all((eg <= GRAD_TOL) | (ek <= 1.0))
 
 
 def test_run_twice_bitwise(ctx6, big_batch, torch):
