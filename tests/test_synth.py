@@ -1,5 +1,6 @@
 """Input generators: determinism, sizes and eligibility (CPU only)."""
 import numpy as np
+import pytest
 
 import synth
 
@@ -42,3 +43,20 @@ def test_make_data_sigma_rule():
     d, sig, w = synth.make_data(f, off, np.zeros(5))
     np.testing.assert_allclose(sig, np.float32([0.05, 0.1, 5.0, 0.05 * 0.05, 0.25]), rtol=1e-6)
     np.testing.assert_allclose(d, f)
+
+
+@pytest.mark.parametrize("which", ["batch_4096_sn", "batch_65536_sn"])
+def test_perturbed_batches_keep_every_band_window_on_the_grid(which):
+    """The gradient workloads evaluate at perturbed parameters: after the redshift steps every
+    observed band's rest-frame window [lo/(1+z), hi/(1+z)] (z as the float32 the GPU gets) still
+    lies on the surface grid, so no evaluation is a range error."""
+    model, bands = synth.make_model(), synth.make_bands(6)
+    base = getattr(synth, which)()
+    for k in (3, 7):
+        b = synth.perturb(base, k=k)
+        z = b.z.astype(np.float64)
+        n_s = np.diff(b.sn_offsets)
+        sn_of = np.repeat(np.arange(b.n_sn), n_s)
+        lo = np.array([bd.lo for bd in bands])[b.band] / (1.0 + z[sn_of])
+        hi = np.array([bd.hi for bd in bands])[b.band] / (1.0 + z[sn_of])
+        assert lo.min() >= model.wave0 and hi.max() <= model.wave_max, (which, k)
