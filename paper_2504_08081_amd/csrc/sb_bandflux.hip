@@ -44,6 +44,11 @@ template <int MODE, bool BCAST, int NW>
 __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int sn, const Lds& L,
                         SnShared& S) {
   constexpr int NR = ModeInfo<MODE>::NR, NT = NW * WAVE;
+  // The adjoint's observation pass always spreads the observations over the
+  // threads of the mode's own wave count, so that each thread's partial sums,
+  // and hence the gradient's summation order, do not depend on how many waves
+  // built the row projections (extra waves contribute exact zeros).
+  constexpr int OBS_NT = MODE == VJP ? (NT < ModeInfo<VJP>::NW * WAVE ? NT : ModeInfo<VJP>::NW * WAVE) : NT;
   const int tid = threadIdx.x;
   const bool chi2 = (b.flags & SB_OUT_CHI2) != 0;
   const float z = b.z[sn], t0 = b.t0[sn], x0 = b.x0[sn], x1 = b.x1[sn], c = b.c[sn];
@@ -76,7 +81,8 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
   }
 
   // scan: bands in use, rows touched; observations with nothing to integrate
-  for (int i = lo + tid; i < hi; i += NT) {
+  // (their chi-square terms join the threads' partial sums: same layout as below)
+  for (int i = lo + tid; tid < OBS_NT && i < hi; i += OBS_NT) {
     const int bd = b.band[i];
     const PhaseCell pc = phase_cell(b.t[i], t0, s64, m);
     const bool bad_band = (unsigned)bd >= (unsigned)m.n_bands;
@@ -112,7 +118,7 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
     __syncthreads();
 
     // every observation of the group's bands, in one pass
-    for (int i = lo + tid; i < hi; i += NT) {
+    for (int i = lo + tid; tid < OBS_NT && i < hi; i += OBS_NT) {
       const int bd = b.band[i];
       if ((unsigned)bd >= (unsigned)m.n_bands) continue;
       const int slot = S.slot_of[bd];
@@ -250,8 +256,17 @@ constexpr int FEW_SN = 64;
 constexpr int FEW_SN_NW = 8;
 constexpr int FLUX_NW = 3;
 
+// An adjoint call on a few supernovae: one wave per band of a group builds the
+// row projections; the observation pass keeps the mode's thread layout
+// (OBS_NT in sn_body), so every result is bit for bit that of the batch kernel.
+constexpr int FEW_SN_VJP_NW = ModeInfo<VJP>::GROUP;
+
 hipError_t launch_sn(bool adj, const KModel& m, const KTables& tb, const KBatch& b, hipStream_t st) {
   const bool bc = (b.flags & SB_OBS_BROADCAST) != 0;
+  if (adj && !bc && b.n_sn <= FEW_SN) {
+    const size_t lds = lds_layout_bytes<VJP>(m.n_phase, tb.max_pts, tb.jcap, FEW_SN_VJP_NW);
+    if (lds <= (size_t)tb.lds_limit) return launch_nw<VJP, false, FEW_SN_VJP_NW>(m, tb, b, lds, st);
+  }
   if (adj) return bc ? launch_one<VJP, true>(m, tb, b, st) : launch_one<VJP, false>(m, tb, b, st);
   if (!bc && !(b.flags & SB_OUT_CHI2)) {
     if (b.n_sn <= FEW_SN) {

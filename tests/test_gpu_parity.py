@@ -415,14 +415,27 @@ def test_results_do_not_depend_on_the_rest_of_the_batch(ctx6, big_batch, torch):
     ctx6.device_check()
 
 
-def test_few_supernova_forward_matches_the_batch_kernel(ctx6, big_batch, torch):
-    """Forward calls on at most 64 supernovae run one wave per band; their fluxes are bitwise those
-    of the same supernovae in the 4,096-supernova batch."""
+def test_few_supernova_calls_match_the_batch_kernel(ctx6, big_batch, torch):
+    """Calls on at most 64 supernovae run more waves per supernova (forward: one per band; adjoint:
+    one per band of a group); their fluxes, and the adjoint's gradients and chi-squares, are bitwise
+    those of the same supernovae in the 4,096-supernova batch."""
+    ev = synth.perturb(big_batch)
+    g = np.random.default_rng(29)
+    data = g.normal(size=ev.n_obs).astype(np.float32)
+    w = np.abs(g.normal(size=ev.n_obs)).astype(np.float32)
     full = ctx6.bandflux(**to_dev(big_batch, torch)).cpu()
+    run = lambda bb, dd, ww: ctx6.bandflux_vjp(**to_dev(bb, torch), chi2=True, data=torch.from_numpy(dd).cuda(),
+                                                inv_sigma2=torch.from_numpy(ww).cuda(), want_flux=True)
+    fullv = run(ev, data, w)
     for idx in (np.array([7]), np.arange(100, 110), np.arange(4032, 4096)):
         sel = np.concatenate([np.arange(big_batch.sn_offsets[i], big_batch.sn_offsets[i + 1]) for i in idx])
         part = ctx6.bandflux(**to_dev(big_batch.subset(idx), torch)).cpu()
         assert torch.equal(part, full[torch.from_numpy(sel)]), len(idx)
+        pv = run(ev.subset(idx), data[sel], w[sel])
+        ti = torch.from_numpy(idx).cuda()
+        assert torch.equal(pv["grad"], fullv["grad"][ti]), len(idx)
+        assert torch.equal(pv["chi2"], fullv["chi2"][ti]), len(idx)
+        assert torch.equal(pv["flux"], fullv["flux"][torch.from_numpy(sel).cuda()]), len(idx)
     ctx6.device_check()
 
 
