@@ -19,6 +19,11 @@ from oracle.salt64 import HC
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
+# Colour-law reference wavelengths (Angstrom), written here as literals.
+LAM_B, LAM_V = 4302.57, 5428.55
+# h c in erg Angstrom: the CODATA value 1.98644586e-25 J m, written here as a literal.
+HC_LITERAL = 1.98644586e-8
+
 
 # ----------------------------------------------------------------------------- helpers
 
@@ -354,7 +359,9 @@ def test_p8_quadrature_converges_to_quad(model):
         mu = lam * s
         v = (mu - 2000.0) / 10.0
         I = oracle.interp2(m0, u, v) + x1f * oracle.interp2(m1, u, v)
-        cl = oracle.colour_law(model, mu)
+        r = (mu - LAM_B) / (LAM_V - LAM_B)           # the colour law written out here
+        a1, a2, a3 = (float(v) for v in model.cl_coef)
+        cl = a1 * r + a2 * r * r + a3 * r * r * r
         return x0f * s * I * np.exp(cf * cl) * lam / HC
 
     nodes = (2000.0 + 10.0 * np.arange(721)) / s
@@ -537,3 +544,138 @@ def test_tiny_exact_fixture_is_its_own_exact_derivation():
         fx = json.load(fh)
     stored = Fraction(fx["expected_flux_times_hc"]["num"], fx["expected_flux_times_hc"]["den"])
     assert mod.derive(fx) == stored
+
+
+# ----------------------------------------------------------------------------- D6 colour law, D8 hc, R7 edge cells
+
+
+
+def test_colour_law_polynomial_values_and_slopes():
+    """CL(mu) = a1 r + a2 r^2 + a3 r^3 with r = (mu - lam_B)/(lam_V - lam_B), evaluated by hand at
+    r = 0, 1, 2 and -1 (values) and its mu-slope at the same points."""
+    a1, a2, a3 = -0.93, 0.047, -0.0061
+    md = synth.Model(m0=np.ones((4, 4), np.float32), m1=np.zeros((4, 4), np.float32),
+                     cl_coef=np.array([a1, a2, a3]))
+    span = 1125.98                                   # lam_V - lam_B, by hand
+    mu = np.array([LAM_B, LAM_V, LAM_B + 2 * span, LAM_B - span])
+    cl, dcl = oracle.colour_law(md, mu, deriv=True)
+    want = [0.0, a1 + a2 + a3, 2 * a1 + 4 * a2 + 8 * a3, -a1 + a2 - a3]
+    np.testing.assert_allclose(cl, want, rtol=1e-12, atol=1e-15)
+    want_d = np.array([a1, a1 + 2 * a2 + 3 * a3, a1 + 4 * a2 + 12 * a3, a1 - 2 * a2 + 3 * a3]) / span
+    np.testing.assert_allclose(dcl, want_d, rtol=1e-12)
+
+
+@pytest.mark.parametrize("z,c", [(0.0, 0.3), (0.25, -0.2), (0.6, 0.45)])
+def test_colour_closed_form_linear_law(z, c):
+    """c != 0 closed form: flat M0 = K, top-hat T on [a, b], linear colour law a1 r.  The integrand
+    K x0 s exp(c a1 (lam s - lam_B)/(lam_V - lam_B)) lam / hc integrates exactly to
+    e^{beta} [e^{kappa lam}(lam/kappa - 1/kappa^2)]_a^b; trapezoid values on refined grids,
+    Richardson-extrapolated, reach it, and the 5 A value is within its O(Delta^2) error."""
+    K, a1 = 0.75, -0.92              # K exact in float32 (the surface is stored in float32)
+    md = const_model(K, cl=(a1,))
+    a, bnd = 3900.0, 5150.0
+    x0 = 2e-5
+    bt = one_sn_batch(np.float32([2.5]), 0, z=z, t0=0.0, x0=x0, x1=0.0, c=c)
+    zf, cf, x0f = (float(np.float32(v)) for v in (z, c, x0))
+    s = 1.0 / (1.0 + zf)
+    kap = cf * a1 * s / (LAM_V - LAM_B)
+    beta = -cf * a1 * LAM_B / (LAM_V - LAM_B)
+    prim = lambda L: np.exp(kap * L) * (L / kap - 1.0 / kap ** 2)
+    exact = x0f * s * K * np.exp(beta) * (prim(bnd) - prim(a)) / HC_LITERAL
+    vals = [oracle.Oracle(md, [synth.tophat_band(a, bnd)], spacing=sp).bandflux(bt)[0] for sp in (5.0, 2.5, 1.25)]
+    rich = (4 * vals[2] - vals[1]) / 3
+    np.testing.assert_allclose(rich, exact, rtol=1e-8)
+    # the plain 5 A trapezoid differs by its Euler-Maclaurin term Delta^2 [g'(b) - g'(a)] / 12,
+    # g(lam) = lam e^{kappa lam}, g' = (1 + kappa lam) e^{kappa lam}
+    gp = lambda L: (1.0 + kap * L) * np.exp(kap * L)
+    scale = x0f * s * K * np.exp(beta) / HC_LITERAL
+    em = 25.0 / 12.0 * (gp(bnd) - gp(a)) * scale
+    np.testing.assert_allclose(vals[0] - exact, em, rtol=2e-3, atol=2e-9 * abs(exact))
+    bound = abs(em)
+    # and the colour term is really present: the c = 0 flux differs by far more than that
+    f0 = oracle.Oracle(md, [synth.tophat_band(a, bnd)]).bandflux(one_sn_batch([2.5], 0, z=z, x0=x0, x1=0.0, c=0.0))
+    assert abs(f0[0] - exact) > 100 * bound
+
+
+def test_colour_cubic_law_against_adaptive_quadrature(model):
+    """c != 0 with the cubic colour law written out in this test (not through the oracle):
+    Richardson-extrapolated trapezoid values equal scipy.quad on the continuous integrand."""
+    a_lo, a_hi = 4210.0, 5570.0
+    band = synth.tophat_band(a_lo, a_hi)
+    z, x0, c = 0.2, 1e-5, 0.35
+    K = 1.25
+    a1, a2, a3 = (float(v) for v in model.cl_coef)
+    md = const_model(K, cl=(a1, a2, a3))
+    bt = one_sn_batch([0.0], 0, z=z, x0=x0, x1=0.0, c=c)
+    zf, x0f, cf = (float(np.float32(v)) for v in (z, x0, c))
+    s = 1.0 / (1.0 + zf)
+
+    def integrand(lam):
+        r = (lam * s - LAM_B) / (LAM_V - LAM_B)
+        cl = a1 * r + a2 * r * r + a3 * r * r * r
+        return x0f * s * K * np.exp(cf * cl) * lam / HC_LITERAL
+
+    ref = integrate.quad(integrand, a_lo, a_hi, epsabs=0, epsrel=1e-13)[0]
+    vals = [oracle.Oracle(md, [band], spacing=sp).bandflux(bt)[0] for sp in (5.0, 2.5, 1.25)]
+    rich = (4 * vals[2] - vals[1]) / 3
+    np.testing.assert_allclose(rich, ref, rtol=1e-8)
+
+
+def test_hc_is_the_physical_constant():
+    """Flat spectrum through a top-hat with hc written as the literal CODATA value: the oracle's
+    flux equals x0 K (b^2 - a^2) / (2 hc (1+z)) to the literal's 9 digits."""
+    K = 0.5
+    md = const_model(K)
+    a, bnd = 4400.0, 6100.0
+    o = oracle.Oracle(md, [synth.tophat_band(a, bnd)])
+    bt = one_sn_batch(np.float32([1.0, 11.0]), 0, z=0.5, t0=0.0, x0=1e-5, x1=0.0, c=0.0)
+    want = float(np.float32(1e-5)) * K * (bnd ** 2 - a ** 2) / (2 * HC_LITERAL * 1.5)
+    np.testing.assert_allclose(o.bandflux(bt), want, rtol=5e-9)
+    assert abs(oracle.HC / HC_LITERAL - 1.0) < 5e-9
+
+
+def _edge_points(n, g, m):
+    """m points in each of the first and last cells (0, 1) and (n-2, n-1), kept off the nodes."""
+    return np.r_[g.uniform(0.05, 0.95, m), g.uniform(n - 1.95, n - 1.05, m)]
+
+
+def test_edge_cell_derivatives_vs_central_differences():
+    """dI/du and dI/dv in the first and last cell of each axis (linear there) against FP64 central
+    differences taken inside the cell."""
+    g = np.random.default_rng(21)
+    n_p, n_w = 9, 11
+    M = g.normal(size=(n_p, n_w))
+    h = 1e-6
+    # phase edge cells, wavelength interior and edge
+    for u, v in ((_edge_points(n_p, g, 20), g.uniform(1.0, n_w - 2.0, 40)),
+                 (g.uniform(1.0, n_p - 2.0, 40), _edge_points(n_w, g, 20)),
+                 (_edge_points(n_p, g, 20), _edge_points(n_w, g, 20))):
+        _, du, dv = oracle.interp2(M, u, v, deriv=True)
+        fd_u = (oracle.interp2(M, u + h, v) - oracle.interp2(M, u - h, v)) / (2 * h)
+        fd_v = (oracle.interp2(M, u, v + h) - oracle.interp2(M, u, v - h)) / (2 * h)
+        np.testing.assert_allclose(du, fd_u, rtol=0, atol=1e-8)
+        np.testing.assert_allclose(dv, fd_v, rtol=0, atol=1e-8)
+        # in an edge cell the derivative along that axis is the node difference (linear piece)
+    u = np.array([0.3, n_p - 1.7])
+    _, du, _ = oracle.interp2(M, u, np.array([4.0, 4.0]), deriv=True)
+    np.testing.assert_allclose(du, [M[1, 4] - M[0, 4], M[n_p - 1, 4] - M[n_p - 2, 4]], rtol=1e-13)
+
+
+def test_edge_cell_partials_of_the_bandflux(model):
+    """d f/d t0 for observations in the first and last phase cell, and d f/dz for bands whose rest
+    window reaches the first or last wavelength cell, against FP64 central differences."""
+    lo_band = synth.tophat_band(2004.0 * 1.3, 2600.0 * 1.3)     # rest window starts in cell 0 at z = 0.3
+    hi_band = synth.tophat_band(8600.0 * 1.3, 9197.0 * 1.3)     # rest window ends in the last cell
+    o = oracle.Oracle(model, [lo_band, hi_band])
+    t = np.float32([-19.6 * 1.3, -19.2 * 1.3, 49.3 * 1.3, 49.8 * 1.3, 10.0 * 1.3])
+    for bd in (0, 1):
+        b = one_sn_batch(t, bd, z=0.3, t0=0.0, x0=1e-5, x1=0.4, c=0.1)
+        P = b.params().astype(np.float64)
+        f, J = o.jac(b, P)
+        for q, h in ((1, 1e-5), (0, 1e-7)):
+            Pp, Pm = P.copy(), P.copy()
+            Pp[:, q] += h
+            Pm[:, q] -= h
+            fd = (o.bandflux(b, Pp) - o.bandflux(b, Pm)) / (2 * h)
+            sc = np.abs(J[:, q]).max()
+            assert np.max(np.abs(fd - J[:, q])) <= 1e-6 * sc, (bd, q, np.max(np.abs(fd - J[:, q])) / sc)
