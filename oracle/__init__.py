@@ -9,3 +9,4 @@ invariants and brute-force exact rational evaluation (tests/test_oracle_pins.py)
 """
 from .salt64 import HC, Oracle, band_grid, colour_law, interp2, segment_sum  # noqa: F401
 from .fit64 import FitOracle  # noqa: F401
+from .lbfgsb64 import lbfgsb  # noqa: F401

@@ -1,4 +1,4 @@
-"""FP64 oracle of the light-curve fit served by the library.
+"""FP64 oracle of the light-curve fits served by the library.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/salt64.py``).
 
@@ -19,11 +19,18 @@ Levenberg-Marquardt damped Gauss-Newton iteration, written here step by step:
 * a subset of the four parameters may be held at its starting value: the
   damped system is then the one of the free parameters alone (the rows and
   columns of H and the entries of g that belong to them).
+
+The second solver is the bounded quasi-Newton method of the paper's
+optimisation example, L-BFGS-B (``oracle/lbfgsb64.py``), on the same unknowns
+and objective chi2(q) with gradient -2 J^T W r, bounds on (t0, x0, x1, c)
+(x0's taken to ln x0), a held parameter being one whose lower and upper bounds
+equal its start, and the same budget: ``iters`` evaluations after the start.
 """
 from __future__ import annotations
 
 import numpy as np
 
+from .lbfgsb64 import lbfgsb
 from .salt64 import Oracle
 
 LAMBDA_MIN, LAMBDA_MAX = 1e-9, 1e9
@@ -97,3 +104,31 @@ class FitOracle:
                 lam = min(lam * 10.0, LAMBDA_MAX)
         theta = np.array([q[0], np.exp(q[1]), q[2], q[3]])
         return dict(theta=theta, chi2=chi2, n_accept=n_acc, status="ok")
+
+
+    def fit_lbfgsb(self, batch, z, theta0, data, inv_sigma2, lower=None, upper=None, iters=50, m=5,
+                   free=(True, True, True, True)):
+        """L-BFGS-B fit from theta0 = (t0, x0, x1, c) within bounds on (t0, x0, x1, c) (None: none;
+        x0's bounds apply to ln x0, a lower bound <= 0 meaning none).  Returns dict(theta, chi2,
+        n_accept, evals, status)."""
+        t0, x0, x1, c = [float(v) for v in theta0]
+        q0 = np.array([t0, np.log(x0), x1, c])
+        lo = np.full(4, -np.inf) if lower is None else np.asarray(lower, np.float64).copy()
+        hi = np.full(4, np.inf) if upper is None else np.asarray(upper, np.float64).copy()
+        lo[1] = np.log(lo[1]) if lo[1] > 0 else -np.inf
+        hi[1] = np.log(hi[1]) if hi[1] > 0 else (-np.inf if hi[1] <= 0 and np.isfinite(hi[1]) else np.inf)
+        for k in range(4):
+            if not free[k]:
+                lo[k] = hi[k] = q0[k]
+
+        def fun(q):
+            chi2, _, g = self.evaluate(batch, z, q, data, inv_sigma2)
+            return chi2, -2.0 * g
+
+        chi2_0, _, _ = self.evaluate(batch, z, np.clip(q0, lo, hi), data, inv_sigma2)
+        if not np.isfinite(chi2_0):
+            return dict(theta=np.array([t0, x0, x1, c]), chi2=chi2_0, n_accept=0, evals=0, status="diverged")
+        r = lbfgsb(fun, q0, lo, hi, m=m, max_evals=iters)
+        q = r["x"]
+        theta = np.array([q[0], np.exp(q[1]) if free[1] else x0, q[2], q[3]])
+        return dict(theta=theta, chi2=r["f"], n_accept=r["n_iter"], evals=r["evals"], status="ok")
