@@ -30,7 +30,8 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 METRIC = "bandflux evals/s (fwd, fwd+adjoint) vs FP64 err; p50/p99 fit latency"
-PEAK_FP32_TFLOPS = 157.3       # MI355X vector FP32 (packed); the build disables packed FP32 (half of it)
+PEAK_FP32_TFLOPS = 157.3       # MI355X vector FP32 (packed)
+PEAK_FP32_UNPACKED_TFLOPS = 78.6   # without packed FP32, which the build disables: the attainable VALU ceiling
 PEAK_HBM_GBS = 8000.0
 
 # Algorithmic work per unit of the implemented algorithm (flops, an FMA counts 2):
@@ -123,6 +124,7 @@ def reference_flops(st, mode):
 
 _OR = None
 _LIMITS = None
+CPU_WORKERS_MAX = 16   # the host CPU share of one GPU on the GPU machines, whatever os.cpu_count() reports
 
 
 def _init_worker():
@@ -133,59 +135,139 @@ def _init_worker():
 
 
 def _oracle_chunk(args):
-    batch, data, w = args
-    return _OR.chi2_grad(batch, data, w)[1].shape[0]
+    kind, batch, data, w = args
+    if kind == "fwd":
+        return _OR[6].bandflux(batch).shape[0]
+    return _OR[6].chi2_grad(batch, data, w)[1].shape[0]
 
 
-def cpu_baseline(batch, model, bands, budget_s):
-    """FP64 oracle chi-square gradient of the whole batch, repeated in full passes until budget_s
-    seconds are spent, over one single-threaded worker process per host core (at most 16)."""
+def _oracle_fit(args):
+    from oracle.fit64 import FitOracle
+    batch, z, theta0, data, w = args
+    return FitOracle(_OR[6]).fit(batch, z, theta0, data, w)["chi2"]
+
+
+def host_cpu():
+    """CPU model and counts of the host the baseline runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "affinity_cpus": aff}
+
+
+def _timed_passes(pool, work, budget_s, n_per_pass):
+    """Full passes of work over the pool until budget_s seconds are spent: (items done, seconds)."""
+    passes = 0
+    t0 = time.perf_counter()
+    while True:
+        for _ in pool.imap_unordered(_oracle_chunk, work):
+            pass
+        passes += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    return passes * n_per_pass, time.perf_counter() - t0, passes
+
+
+def cpu_baseline(batch, truth, model, bands, budget_s):
+    """The FP64 oracle on the host cores, one single-threaded worker process per core (at most the
+    GPU's CPU share): the metric's workload (chi-square gradient of the 4,096-supernova batch, full
+    passes for about budget_s seconds) as `value`, and beside it the one-supernova call, the
+    forward pass of the same batch, 200 fits of the serving workload and a 16,384-sample subset of
+    the sweep."""
     global _OR
     import multiprocessing as mp
 
     import oracle
-    _OR = oracle.Oracle(model, bands)
-    cores = min(16, os.cpu_count() or 1)
+    _OR = {6: oracle.Oracle(model, bands)}
+    host = host_cpu()
+    cores = max(1, min(CPU_WORKERS_MAX, host["affinity_cpus"]))
     chunk = 16
     n_chunks = (batch.n_sn + chunk - 1) // chunk
-    work = []
-    for c in range(n_chunks):
-        sub = batch.subset(np.arange(c * chunk, min(batch.n_sn, (c + 1) * chunk)))
-        work.append((sub, np.zeros(sub.n_obs), np.ones(sub.n_obs)))
+    subs = [batch.subset(np.arange(c * chunk, min(batch.n_sn, (c + 1) * chunk))) for c in range(n_chunks)]
+    tsubs = [truth.subset(np.arange(c * chunk, min(truth.n_sn, (c + 1) * chunk))) for c in range(n_chunks)]
+    grad_work = [("grad", sb, np.zeros(sb.n_obs), np.ones(sb.n_obs)) for sb in subs]
+    fwd_work = [("fwd", sb, None, None) for sb in tsubs]
+    legs = {}
     ctx = mp.get_context("fork")
-    passes = 0
-    t0 = time.perf_counter()
     pool = ctx.Pool(cores, initializer=_init_worker)
     try:
-        while True:
-            for _ in pool.imap_unordered(_oracle_chunk, work):
-                pass
-            passes += 1
-            if time.perf_counter() - t0 >= budget_s:
-                break
+        done, dt, passes = _timed_passes(pool, grad_work, budget_s, batch.n_obs)
+        value = done / dt
+        sample = (f"FP64 oracle forward+adjoint (chi2 gradient), {passes} full passes over the {batch.n_sn} "
+                  f"supernovae ({batch.n_obs} observations each pass) in {dt:.1f} s, {cores} single-threaded "
+                  f"worker processes")
+        done, dt, passes = _timed_passes(pool, fwd_work, 0.2 * budget_s, truth.n_obs)
+        legs["fwd_4096sn"] = {"value": done / dt, "unit": "evals/s",
+                              "sample": f"forward only, {passes} full passes over the batch in {dt:.1f} s"}
+        # 200 fits of the serving workload (50 LM iterations each), noise-free starts as in the bench leg
+        reqs = synth.fit_requests(200, k=4)
+        jobs = []
+        for r in reqs:
+            n = len(r.t)
+            b1 = synth.Batch(np.float32([r.z]), np.float32([r.theta_true[0]]), np.float32([r.theta_true[1]]),
+                             np.float32([r.theta_true[2]]), np.float32([r.theta_true[3]]), r.t, r.band,
+                             np.int32([0, n]))
+            f = _OR[6].bandflux(b1)
+            d, _, w = synth.make_data(f, [0, n], r.normals)
+            jobs.append((b1, r.z, r.theta_init, d, w))
+        t0 = time.perf_counter()
+        pool.map(_oracle_fit, jobs, chunksize=1)
+        dt = time.perf_counter() - t0
+        legs["fits_200"] = {"value": len(jobs) / dt, "unit": "fits/s",
+                            "sample": f"200 requests of the serving workload, FP64 LM fits of 50 iterations, "
+                                      f"in {dt:.1f} s"}
+        # the sweep: a 16,384-sample subset of the 1,048,576 samples, 120 observations each
+        sw = synth.sweep_120_obs(n_samples=16384)
+        smp, no = sw.samples, len(sw.obs_t)
+        sw_work = []
+        for lo in range(0, smp.n_sn, 256):
+            idx = np.arange(lo, min(smp.n_sn, lo + 256))
+            m = len(idx)
+            sw_work.append(("fwd", synth.Batch(smp.z[idx], smp.t0[idx], smp.x0[idx], smp.x1[idx], smp.c[idx],
+                                               np.tile(sw.obs_t, m), np.tile(sw.obs_band, m),
+                                               np.arange(0, (m + 1) * no, no, dtype=np.int32)), None, None))
+        t0 = time.perf_counter()
+        for _ in pool.imap_unordered(_oracle_chunk, sw_work):
+            pass
+        dt = time.perf_counter() - t0
+        legs["sweep_subset"] = {"value": smp.n_sn * no / dt, "unit": "evals/s",
+                                "sample": f"subset: {smp.n_sn} of the 1,048,576 samples x {no} observations "
+                                          f"in {dt:.1f} s"}
     finally:
         pool.close()
         pool.join()
-    dt = time.perf_counter() - t0
-    done_obs = passes * batch.n_obs
-    return {"value": done_obs / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle forward+adjoint (chi2 gradient), {passes} full passes over the "
-                      f"{batch.n_sn} supernovae ({batch.n_obs} observations each pass) in {dt:.1f} s, "
-                      f"{cores} single-threaded worker processes"}
+    # one supernova, 40 observations in 4 bands: one call on one core
+    o4 = oracle.Oracle(model, synth.make_bands(4))
+    b1 = synth.one_sn_40_obs()
+    o4.bandflux(b1)
+    t0 = time.perf_counter()
+    for _ in range(50):
+        o4.bandflux(b1)
+    legs["one_sn_40_obs"] = {"value": (time.perf_counter() - t0) / 50 * 1e6, "unit": "us per call",
+                             "sample": "50 calls of the forward pass on one core"}
+    return {"value": value, "unit": "evals/s", "cores": cores, "kind": "oracle", "sample": sample,
+            "host": host, "legs": legs}
 
 
-def _cpu_baseline_child(conn, batch, model, bands, budget_s):
-    conn.send(cpu_baseline(batch, model, bands, budget_s))
+def _cpu_baseline_child(conn, batch, truth, model, bands, budget_s):
+    conn.send(cpu_baseline(batch, truth, model, bands, budget_s))
     conn.close()
 
 
-def cpu_baseline_isolated(batch, model, bands, budget_s):
+def cpu_baseline_isolated(batch, truth, model, bands, budget_s):
     """cpu_baseline in a child process that has exited (with its workers and any BLAS threads) before
     this process touches the GPU, so no host load is left behind for the timed GPU legs."""
     import multiprocessing as mp
     ctx = mp.get_context("fork")
     rx, tx = ctx.Pipe(duplex=False)
-    proc = ctx.Process(target=_cpu_baseline_child, args=(tx, batch, model, bands, budget_s))
+    proc = ctx.Process(target=_cpu_baseline_child, args=(tx, batch, truth, model, bands, budget_s))
     proc.start()
     tx.close()
     res = rx.recv()
@@ -220,20 +302,25 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def profiled_traffic(path):
-    """HBM bytes per launch recorded with the rocprofv3 FETCH_SIZE / WRITE_SIZE passes, or None if
-    there is no record or the kernels have changed since it was taken."""
+def profile_record(path):
+    """The machine-readable lines of a committed rocprofv3 summary (HBM bytes and executed FP32 flops
+    per launch), or {} if there is none or the kernels have changed since it was taken."""
     if not os.path.exists(path):
-        return None
+        return {}
     rec = {}
     with open(path) as fh:
         for line in fh:
             k, _, v = line.partition(":")
-            if k.strip() in ("kernel_sources_sha256", "traffic_bytes_per_launch"):
+            if k.strip() in ("kernel_sources_sha256", "traffic_bytes_per_launch", "executed_fp32_flops_per_launch"):
                 rec[k.strip()] = v.strip()
-    if rec.get("kernel_sources_sha256") != kernel_sources_sha256() or "traffic_bytes_per_launch" not in rec:
-        return None
-    return int(rec["traffic_bytes_per_launch"])
+    if rec.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return {}
+    out = {}
+    if "traffic_bytes_per_launch" in rec:
+        out["traffic"] = int(rec["traffic_bytes_per_launch"])
+    if "executed_fp32_flops_per_launch" in rec:
+        out["executed_flops"] = float(rec["executed_fp32_flops_per_launch"])
+    return out
 
 
 # ----------------------------------------------------------------------------- timing helpers
@@ -260,7 +347,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--sweep-samples", type=int, default=1 << 20)
@@ -283,7 +370,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: FP64 oracle on the host cores ...")
-        cpu = cpu_baseline_isolated(ev_params, model, bands, args.cpu_seconds)
+        cpu = cpu_baseline_isolated(ev_params, truth, model, bands, args.cpu_seconds)
         log(f"cpu baseline: {cpu['value']:.0f} evals/s on {cpu['cores']} cores")
 
     import torch
@@ -344,7 +431,14 @@ def main():
     value = n_obs * args.steps / wall
     st = group_stats(ev_params, lam_grids, model)
     kern_s = float(durs.mean()) * 1e-3
-    flops = algorithmic_flops(st, "vjp")
+    alg_flops = algorithmic_flops(st, "vjp")
+    ref_flops = reference_flops(st, "vjp")
+    prof = profile_record(PROFILE_VJP)
+    if "executed_flops" in prof:
+        flops, src = prof["executed_flops"], ("executed FP32 flops per launch (FMA 2, add and mul 1, 64 lanes) from "
+                                              "the rocprofv3 counters of the same kernels, profiles/k_sn_vjp_4096sn.md")
+    else:
+        flops, src = alg_flops, "implemented algorithm's flop count (no counter profile of the current kernels)"
     achieved = flops / kern_s / 1e12
     result = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
@@ -353,16 +447,22 @@ def main():
         "config": {"workload": "fwd+adjoint chi2 gradient, 4096 SN, uneven 20-200 obs, 6 bands",
                    "n_sn": truth.n_sn, "n_obs": n_obs, "bands": 6, "surface": "71x721", "parallelism": "none"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": profiled_traffic(PROFILE_VJP),
-                     "kernel": "k_sn<VJP>", "kernel_ms": float(durs.mean()),
-                     "flops_per_launch": flops, "work": st},
-        "reference_count_tflops": reference_flops(st, "vjp") / kern_s / 1e12,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": prof.get("traffic"),
+                     "achieved_source": src, "kernel": "k_sn<VJP>", "kernel_ms": float(durs.mean()),
+                     "flops_per_launch": flops,
+                     "attainable_peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
+                     "frac_of_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS,
+                     "reference_count": {"flops_per_launch": ref_flops, "tflops": ref_flops / kern_s / 1e12,
+                                         "frac": ref_flops / kern_s / 1e12 / PEAK_FP32_TFLOPS,
+                                         "per_obs": "40 J + 90 N (direct form, forward + adjoint)"},
+                     "implemented_algorithm": {"flops_per_launch": alg_flops, "tflops": alg_flops / kern_s / 1e12},
+                     "work": st},
         "kernel_evals_per_s": n_obs / kern_s,
         "timing": f"value: {args.steps} steps as {args.steps // G} replays of a HIP graph of {G} launches; "
                   "kernel_ms: HIP events around each of as many eager launches",
         "eager_evals_per_s": n_obs * args.steps / wall_eager,
     }
-    log(f"main: {value:.3e} evals/s, kernel {durs.mean():.4f} ms, {achieved:.2f} TFLOP/s algorithmic")
+    log(f"main: {value:.3e} evals/s, kernel {durs.mean():.4f} ms, {achieved:.2f} TFLOP/s ({src[:40]})")
 
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
@@ -498,11 +598,12 @@ def serve_leg(torch, saltbf, model, bands, seconds, **config):
     normals = np.concatenate([r.normals for r in reqs])
     data, sig, _ = synth.make_data(f, off, normals)
     tickets = []
-    t_start = time.perf_counter()
+    # the library stamps t_submit / t_admit / t_done with the monotonic clock, which time.monotonic reads
+    t_start = time.monotonic()
     for i, r in enumerate(reqs):
         target = t_start + r.arrival
         while True:
-            now = time.perf_counter()
+            now = time.monotonic()
             if now >= target:
                 break
             if target - now > 2e-4:
@@ -513,13 +614,20 @@ def serve_leg(torch, saltbf, model, bands, seconds, **config):
     stats = ctx.stats()
     ctx.close()
     warm = int(1.0 * rate)
-    lat = np.array([(x.t_done - x.t_submit) for x in res[warm:] if x is not None]) * 1e3
-    queue = np.array([(x.t_admit - x.t_submit) for x in res[warm:] if x is not None]) * 1e3
+    meas = [(x, t_start + r.arrival) for x, r in zip(res[warm:], reqs[warm:]) if x is not None]
+    # latency from the scheduled Poisson arrival (includes any delay before the submit call)
+    lat = np.array([x.t_done - arr for x, arr in meas]) * 1e3
+    lat_sub = np.array([x.t_done - x.t_submit for x, _ in meas]) * 1e3
+    lag = np.array([x.t_submit - arr for x, arr in meas]) * 1e3
+    queue = np.array([(x.t_admit - x.t_submit) for x, _ in meas]) * 1e3
     done = [x for x in res if x is not None]
     span = max(x.t_done for x in done) - min(x.t_submit for x in done)
     ok = sum(1 for x in done if x.status == 0)
     return {"requests": n_req, "rate_req_s": rate, "completed_ok": ok, "fits_per_s": len(done) / span,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "latency_from": "scheduled arrival",
+            "submit_p50_ms": float(np.percentile(lat_sub, 50)), "submit_p99_ms": float(np.percentile(lat_sub, 99)),
+            "submit_lag_p99_ms": float(np.percentile(lag, 99)),
             "mean_queue_ms": float(queue.mean()), "ticks": stats["ticks"],
             "mean_active_slots_per_tick": stats["slot_ticks"] / max(1, stats["ticks"])}
 

@@ -230,6 +230,45 @@ sb_status sb_fit_wait(sb_ctx *ctx, uint64_t ticket, double timeout_s, sb_fit_res
 /* Cancel a queued or running fit; its result becomes SB_CANCELLED. */
 sb_status sb_fit_cancel(sb_ctx *ctx, uint64_t ticket);
 
+/* ------------------------------------------------------------ batch fits
+ * The same fit as the server's, run over a whole batch of supernovae already on
+ * the device (throughput rather than latency: one call fits every light curve of
+ * a survey batch).  Fit f has observations [fit_offsets[f], fit_offsets[f+1]) of
+ * the CSR arrays t, band, data, inv_sigma2 (all device, as in sb_batch),
+ * fixed redshift z[f], start (t0[f], x0[f] > 0, x1[f], c[f]) and free_mask[f]
+ * (SB_FREE_* bits, 0 = all; the array may be NULL: all free).  The call enqueues
+ * ceil(cfg.fit_iters / cfg.iters_per_tick) launches (at least one) on
+ * hip_stream, each running cfg.iters_per_tick iterations of every fit, with each
+ * fit's state kept in device scratch between launches; a fit's result is
+ * bitwise the same whichever other fits share the call.  Malformed device
+ * inputs (band ids, CSR offsets, band windows off the surface) give NaN results
+ * and the sticky flags of sb_device_check. */
+typedef struct {
+  int32_t n_fit, n_obs;
+  const float *z, *t0, *x0, *x1, *c;   /* device [n_fit] */
+  const uint32_t *free_mask;           /* device [n_fit] or NULL */
+  const float *t;                      /* device [n_obs] */
+  const int32_t *band;                 /* device [n_obs] */
+  const int32_t *fit_offsets;          /* device CSR [n_fit + 1] */
+  const float *data, *inv_sigma2;      /* device [n_obs] */
+} sb_fit_batch_desc;
+
+/* One fit's result (device array [n_fit] written by the last launch). */
+typedef struct {
+  float t0, x0, x1, c;       /* fitted parameters (a held one as given) */
+  float chi2;                /* at the fitted parameters */
+  int32_t status;            /* SB_OK or SB_FIT_DIVERGED */
+  int32_t iters;             /* iterations run */
+  int32_t n_accept;          /* accepted steps */
+} sb_fit_out;
+
+/* Fits every supernova of the batch (see above).  The per-fit state scratch
+ * (cfg-independent, about 128 bytes per fit) is allocated stream-ordered for the
+ * call and released after its last launch.  Asynchronous; out must stay valid
+ * until the stream reaches the end of the call's work.  SB_ERR_ARG for NULL
+ * pointers or sizes; n_fit = 0 does nothing. */
+sb_status sb_fit_batch(sb_ctx *ctx, const sb_fit_batch_desc *batch, sb_fit_out *out, void *hip_stream);
+
 typedef struct {
   int64_t submitted, admitted, completed, cancelled, rejected;
   int64_t ticks;               /* server launches */

@@ -137,21 +137,24 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
         cr_weights(pc.x, pc.edge, wp);
         const int tb0 = pc.edge ? 1 : 0, tb1 = pc.edge ? 3 : 4;
         float Sx = 0.f;
-        if (MODE == FWD) {
+        if constexpr (MODE == FWD) {
           for (int t = tb0; t < tb1; ++t) Sx = fmaf(wp[t], Rb[row_clamp(pc.a - 1 + t, rlo, rhi) * NR], Sx);
           f = A * Sx;
         } else {
-          float dw[4];
-          cr_dweights(pc.x, pc.edge, dw);
           float S1 = 0.f, Sc = 0.f, Sl = 0.f, Sp = 0.f;
           for (int t = tb0; t < tb1; ++t) {
             const float* r = Rb + row_clamp(pc.a - 1 + t, rlo, rhi) * NR;
             Sx = fmaf(wp[t], r[0], Sx);
-            Sp = fmaf(dw[t], r[0], Sp);
             S1 = fmaf(wp[t], r[1], S1);
             Sc = fmaf(wp[t], r[2], Sc);
-            if (MODE == VJP) Sl = fmaf(wp[t], r[3], Sl);
+            Sl = fmaf(wp[t], r[3], Sl);
           }
+          // the phase derivative on the projected phase differences Rd (rows rlo .. rhi-1):
+          // sum_t dw_t R(a-1+t) = sum_{t<3} e_t Rd(a-1+t); edge cells: Rd(a)
+          float e[3];
+          cr_diff_weights(pc.x, pc.edge, e);
+#pragma unroll
+          for (int t = 0; t < 3; ++t) Sp = fmaf(e[t], Rb[row_clamp(pc.a - 1 + t, rlo, rhi - 1) * NR + 4], Sp);
           Sp *= m.inv_dphase;
           f = A * Sx;
           const float As = A * s;

@@ -38,14 +38,15 @@ __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 // Which row projections a pass computes.
 //   FWD: Rx                       (flux)
 //   FIT: Rx, R1, Rc               (flux, d/dx1, d/dc; d/dt0 from the phase weights)
-//   VJP: Rx, R1, Rc, Rl           (all five partials, including z)
+//   VJP: Rx, R1, Rc, Rl, Rd       (all five partials, including z; Rd projects the phase
+//                                  first differences of the nodes, for d/dt0 and d/dz)
 enum Mode { FWD = 0, FIT = 1, VJP = 2 };
 
 // Per mode: NG weight vectors, interleaved per point tap and per window column
 // as one vector type (float / float2 / float4), and NR row projections.
 //   FWD: G                  | Rx
 //   FIT: G, Gc              | Rx, R1, Rc
-//   VJP: G, Gc, Glc, Gd     | Rx, R1, Rc, Rl
+//   VJP: G, Gc, Glc, Gd     | Rx, R1, Rc, Rl, Rd
 template <int MODE> struct ModeInfo;
 // A workgroup of NW waves (fewer if the LDS for NW waves does not fit; see the
 // launches) evaluates one supernova; the bands of a group are
@@ -60,7 +61,7 @@ template <int MODE> struct ModeInfo;
 // surface.
 template <> struct ModeInfo<FWD> { static constexpr int NG = 1, NR = 1, NW = 2, GROUP = 8, CW = 4; typedef float V; };
 template <> struct ModeInfo<FIT> { static constexpr int NG = 2, NR = 3, NW = 8, GROUP = 8, CW = 4; typedef float2 V; };
-template <> struct ModeInfo<VJP> { static constexpr int NG = 4, NR = 4, NW = 2, GROUP = 4, CW = 4; typedef float4 V; };
+template <> struct ModeInfo<VJP> { static constexpr int NG = 4, NR = 5, NW = 2, GROUP = 4, CW = 4; typedef float4 V; };
 
 // Largest group over the modes (sizes the per-slot flags).
 constexpr int BAND_GROUP = 8;
@@ -287,7 +288,7 @@ __device__ inline void load_cols(float2 (&v)[CW], __amdgpu_buffer_rsrc_t rs, uns
 // One window column of the forward / fit row projections: node mc = (M0, M1)
 // of the lane's row, weight vector g.
 template <int MODE>
-__device__ inline void col_step(float (&acc)[4], typename ModeInfo<MODE>::V g, float2 mc, float x1) {
+__device__ inline void col_step(float (&acc)[5], typename ModeInfo<MODE>::V g, float2 mc, float x1) {
   const float mx = fmaf(x1, mc.y, mc.x);
   if constexpr (MODE == FWD) {
     acc[0] = fmaf(g, mx, acc[0]);
@@ -300,7 +301,7 @@ __device__ inline void col_step(float (&acc)[4], typename ModeInfo<MODE>::V g, f
 
 // CW columns held in v; column u goes to chain u mod 4.
 template <int MODE, int CW>
-__device__ inline void chunk_cols(float (&acc)[4][4], const typename ModeInfo<MODE>::V* g, const float2 (&v)[CW],
+__device__ inline void chunk_cols(float (&acc)[4][5], const typename ModeInfo<MODE>::V* g, const float2 (&v)[CW],
                                   float x1) {
 #pragma unroll
   for (int u = 0; u < CW; ++u) col_step<MODE>(acc[u & 3], g[u], v[u], x1);
@@ -308,11 +309,19 @@ __device__ inline void chunk_cols(float (&acc)[4][4], const typename ModeInfo<MO
 
 // The last rem (< CW, uniform) columns, held in v[0..rem-1].
 template <int MODE, int CW>
-__device__ inline void tail_cols(float (&acc)[4][4], const typename ModeInfo<MODE>::V* g, const float2 (&v)[CW],
+__device__ inline void tail_cols(float (&acc)[4][5], const typename ModeInfo<MODE>::V* g, const float2 (&v)[CW],
                                  int rem, float x1) {
 #pragma unroll
   for (int u = 0; u < CW - 1; ++u)
     if (u < rem) col_step<MODE>(acc[u & 3], g[u], v[u], x1);
+}
+
+// The combined node of the next row (lane + 1) minus this lane's: one DPP
+// wave shift (lane L reads lane L + 1; the last lane reads 0 and its value is
+// never used).
+__device__ inline float next_row_diff(float mx) {
+  const float nx = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(mx), 0x130, 0xF, 0xF, true));
+  return nx - mx;
 }
 
 // One window column j of the adjoint's row projections from the lane's row
@@ -320,9 +329,11 @@ __device__ inline void tail_cols(float (&acc)[4][4], const typename ModeInfo<MOD
 // (M0 + x1 M1)(j-1) and difference weight gdp: the first difference of the
 // combined nodes, mx(j) - mx(j-1), is formed here and its term goes to the
 // previous column's chain, after that column's own terms, so every chain sums
-// in column order.  Chains are window columns mod 4 (U = this one's).
+// in column order.  The phase first difference mx(a+1, j) - mx(a, j) (the next
+// row is the next lane) goes to Rd with the flux weight.  Chains are window
+// columns mod 4 (U = this one's).
 template <int U>
-__device__ inline void col_step_d(float (&acc)[4][4], float4 g, float2 cur, float& prev, float& gdp, float x1) {
+__device__ inline void col_step_d(float (&acc)[4][5], float4 g, float2 cur, float& prev, float& gdp, float x1) {
   constexpr int P = (U + 3) & 3;
   const float mx = fmaf(x1, cur.y, cur.x);
   acc[P][3] = fmaf(gdp, mx - prev, acc[P][3]);
@@ -330,12 +341,13 @@ __device__ inline void col_step_d(float (&acc)[4][4], float4 g, float2 cur, floa
   acc[U][1] = fmaf(g.x, cur.y, acc[U][1]);
   acc[U][2] = fmaf(g.y, mx, acc[U][2]);
   acc[U][3] = fmaf(g.z, mx, acc[U][3]);
+  acc[U][4] = fmaf(g.x, next_row_diff(mx), acc[U][4]);
   prev = mx;
   gdp = g.w;
 }
 
 template <int CW>
-__device__ inline void chunk_cols_d(float (&acc)[4][4], const float4* g, const float2 (&v)[CW], float& prev,
+__device__ inline void chunk_cols_d(float (&acc)[4][5], const float4* g, const float2 (&v)[CW], float& prev,
                                     float& gdp, float x1) {
   static_assert(CW == 4, "one chunk is one column per chain");
   col_step_d<0>(acc, g[0], v[0], prev, gdp, x1);
@@ -348,13 +360,13 @@ __device__ inline void chunk_cols_d(float (&acc)[4][4], const float4* g, const f
 // of the column after the window, nx.  Its weight is zero; the term is kept so that every chain
 // ends as the column loop leaves it.
 template <int P>
-__device__ inline void close_chain(float (&acc)[4][4], float2 nx, float prev, float gdp, float x1) {
+__device__ inline void close_chain(float (&acc)[4][5], float2 nx, float prev, float gdp, float x1) {
   acc[P][3] = fmaf(gdp, fmaf(x1, nx.y, nx.x) - prev, acc[P][3]);
 }
 
 // The last rem (< 4) window columns, held in v[0 .. rem-1], and the closing
 // difference term from v[rem] (branches on the uniform rem, static indices only).
-__device__ inline void tail_cols_d(float (&acc)[4][4], const float4* g, const float2 (&v)[4], int rem,
+__device__ inline void tail_cols_d(float (&acc)[4][5], const float4* g, const float2 (&v)[4], int rem,
                                    float& prev, float& gdp, float x1) {
   if (rem == 0) {
     close_chain<3>(acc, v[0], prev, gdp, x1);
@@ -442,6 +454,7 @@ __device__ inline int point_setup(const KModel& m, double s, float c, float2 clq
 //   r=2  sum_j Gc(j) (M0 + x1 M1)[a, j]                (FIT, VJP)
 //   r=3  sum_j Glc(j) (M0 + x1 M1)[a, j]
 //        + sum_j Gd(j) D[a, j]                         (VJP)
+//   r=4  sum_j G(j) ((M0 + x1 M1)[a+1, j] - (M0 + x1 M1)[a, j])   (VJP, rows a < rhi)
 // with om_k = W_k exp(c CL(mu_k)) and
 //   G(j)   = sum_k om_k wl_j(mu_k),          Gc(j) = sum_k om_k CL(mu_k) wl_j(mu_k),
 //   Glc(j) = sum_k om_k mu_k c CL'(mu_k) wl_j(mu_k),
@@ -564,20 +577,22 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   const int nrow = rhi - rlo + 1;
   if constexpr (MODE == VJP) {
     // the adjoint reads the node surface like the other modes and forms the
-    // first differences of the combined nodes on the way (see col_step_d)
+    // first differences of the combined nodes on the way (see col_step_d).  A
+    // pass covers 64 rows and advances by 63: the phase difference of a pass's
+    // last row needs the row after it, which the next pass holds in its first lane.
     const int cstride = m.row_pad * (int)sizeof(float2);
     const int n4 = J >> 2, rem = J & 3;
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void*)tb.surf, 0, tb.surf_bytes, BUF_RSRC_WORD3);
-    for (int rb = 0; rb < nrow; rb += 64) {
+    for (int rb = 0;; rb += WAVE - 1) {
       const int a = rlo + rb + lane;
       const unsigned loff = rb + lane < nrow ? (unsigned)a * (unsigned)sizeof(float2) : BUF_OFF_NONE;
       const int cb = j_lo * cstride;
-      float acc[4][4];
+      float acc[4][5];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[u][r] = 0.f;
+        for (int r = 0; r < 5; ++r) acc[u][r] = 0.f;
       float prev = 0.f;
       float gdp = 0.f;
       float2 A[4], B[4];
@@ -598,8 +613,12 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
       }
       if (rb + lane < nrow) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) Rb[a * NR + r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
+        for (int r = 0; r < NR - 1; ++r) Rb[a * NR + r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
       }
+      // Rd(a) for a < rhi (the last row has no successor)
+      if (lane < WAVE - 1 && rb + lane < nrow - 1)
+        Rb[a * NR + 4] = (acc[0][4] + acc[1][4]) + (acc[2][4] + acc[3][4]);
+      if (rb + WAVE - 1 >= nrow - 1) break;
     }
     wave_sync();
     return true;
@@ -612,11 +631,11 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
     const int a = rlo + rb + lane;
     const unsigned loff = rb + lane < nrow ? (unsigned)a * (unsigned)sizeof(float2) : BUF_OFF_NONE;
     const int cb = j_lo * cstride;
-    float acc[4][4];
+    float acc[4][5];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[u][r] = 0.f;
+      for (int r = 0; r < 5; ++r) acc[u][r] = 0.f;
     float2 A[CW], B[CW];
     load_cols<CW>(A, rs, loff, cb, cstride);
     int c = 0;

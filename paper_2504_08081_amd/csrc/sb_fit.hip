@@ -50,7 +50,13 @@ __device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, cons
   for (int i = tid; i < O.n; i += NT) {
     const int bd = O.band[i];
     const PhaseCell pc = phase_cell(O.t[i], t0, s64, m);
-    if (!pc.in || pc.nan || (unsigned)bd >= (unsigned)m.n_bands) {
+    if ((unsigned)bd >= (unsigned)m.n_bands || pc.nan) {
+      // only device-resident batches can hold these (the server checks its requests)
+      if ((unsigned)bd >= (unsigned)m.n_bands) atomicOr(F.err, EFLAG_BAND);
+      out[14] = __builtin_nanf("");
+      continue;
+    }
+    if (!pc.in) {
       const float r = O.data[i];
       out[14] = fmaf(r * r, O.w[i], out[14]);
       continue;
@@ -199,34 +205,62 @@ __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F)
   // no band's point data in this launch's scratch yet (read after the first barrier)
   if ((threadIdx.x & (WAVE - 1)) == 0) L.tag[0] = -1;
   const int tid = threadIdx.x;
-  FitSlot* sl = F.slots + F.active[blockIdx.x];
-  const int adm = uni(F.admit[blockIdx.x]);
+  const bool batch = F.b_off != nullptr;
+  const int f = blockIdx.x;
+  FitSlot* sl = F.slots + (batch ? f : F.active[f]);
+  const int adm = batch ? -1 : uni(F.admit[f]);
   FitObs O;
   float z;
   // the LM state; every thread holds the same values
   float q[4], H[10], g[4], lambda, chi2;
-  int iter, n_acc, status, free_mask;
-  if (adm >= 0) {
-    // first launch of this fit: move its observations from the inbox to the arena
-    const AdmitHeader h = F.hdr[adm];
-    for (int i = tid; i < h.n_obs; i += NT) {
-      F.t[h.arena_off + i] = F.in_t[h.src_off + i];
-      F.band[h.arena_off + i] = F.in_band[h.src_off + i];
-      F.data[h.arena_off + i] = F.in_data[h.src_off + i];
-      F.w[h.arena_off + i] = F.in_w[h.src_off + i];
+  int iter, n_acc, status, free_mask, obs_off = 0;
+  bool bad_csr = false;
+  const bool start = batch ? (F.b_first != 0) : (adm >= 0);
+  if (start) {
+    if (batch) {
+      // first launch of a batch fit: its observations are the caller's CSR range
+      int lo = F.b_off[f], hi = F.b_off[f + 1];
+      bad_csr = lo < 0 || hi < lo || hi > F.b_n_obs;
+      if (bad_csr) {
+        if (tid == 0) atomicOr(F.err, EFLAG_CSR);
+        lo = hi = 0;
+      }
+      O.t = F.b_t + lo;
+      O.band = F.b_band + lo;
+      O.data = F.b_data + lo;
+      O.w = F.b_w + lo;
+      O.n = hi - lo;
+      obs_off = lo;
+      z = F.b_z[f];
+      q[0] = F.b_t0[f];
+      q[1] = (float)log((double)F.b_x0[f]);
+      q[2] = F.b_x1[f];
+      q[3] = F.b_c[f];
+      const int fm = F.b_free ? (int)(F.b_free[f] & (unsigned)SB_FREE_ALL) : 0;
+      free_mask = fm == 0 ? SB_FREE_ALL : fm;
+    } else {
+      // first launch of a served fit: move its observations from the inbox to the arena
+      const AdmitHeader h = F.hdr[adm];
+      for (int i = tid; i < h.n_obs; i += NT) {
+        F.t[h.arena_off + i] = F.in_t[h.src_off + i];
+        F.band[h.arena_off + i] = F.in_band[h.src_off + i];
+        F.data[h.arena_off + i] = F.in_data[h.src_off + i];
+        F.w[h.arena_off + i] = F.in_w[h.src_off + i];
+      }
+      // this launch reads the inbox copy; the arena copy serves the later launches
+      O.t = F.in_t + h.src_off;
+      O.band = F.in_band + h.src_off;
+      O.data = F.in_data + h.src_off;
+      O.w = F.in_w + h.src_off;
+      O.n = h.n_obs;
+      obs_off = h.arena_off;
+      z = h.z;
+      q[0] = h.t0;
+      q[1] = h.lnx0;
+      q[2] = h.x1;
+      q[3] = h.c;
+      free_mask = h.free_mask;
     }
-    // this launch reads the inbox copy; the arena copy serves the later launches
-    O.t = F.in_t + h.src_off;
-    O.band = F.in_band + h.src_off;
-    O.data = F.in_data + h.src_off;
-    O.w = F.in_w + h.src_off;
-    O.n = h.n_obs;
-    z = h.z;
-    q[0] = h.t0;
-    q[1] = h.lnx0;
-    q[2] = h.x1;
-    q[3] = h.c;
-    free_mask = h.free_mask;
 #pragma unroll
     for (int k = 0; k < 10; ++k) H[k] = 0.f;
 #pragma unroll
@@ -236,11 +270,18 @@ __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F)
     iter = -1;
     n_acc = 0;
     status = SB_OK;
+    if (uni(bad_csr ? 1 : 0)) {
+      // malformed offsets: no observations to fit
+      chi2 = __builtin_nanf("");
+      iter = 0;
+      status = SB_FIT_DIVERGED;
+    }
   } else {
-    O.t = F.t + sl->obs_off;
-    O.band = F.band + sl->obs_off;
-    O.data = F.data + sl->obs_off;
-    O.w = F.w + sl->obs_off;
+    obs_off = sl->obs_off;
+    O.t = (batch ? F.b_t : F.t) + obs_off;
+    O.band = (batch ? F.b_band : F.band) + obs_off;
+    O.data = (batch ? F.b_data : F.data) + obs_off;
+    O.w = (batch ? F.b_w : F.w) + obs_off;
     O.n = sl->n_obs;
     z = sl->z;
 #pragma unroll
@@ -303,7 +344,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F)
   }
   if (tid == 0) {
     FitSlot st;
-    st.obs_off = adm >= 0 ? F.hdr[adm].arena_off : sl->obs_off;
+    st.obs_off = obs_off;
     st.n_obs = O.n;
     st.iter = iter;
     st.n_accept = n_acc;
@@ -317,8 +358,23 @@ __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F)
     for (int k = 0; k < 10; ++k) st.H[k] = H[k];
     for (int k = 0; k < 4; ++k) st.g[k] = g[k];
     *sl = st;
-    const int oi = F.out_idx[blockIdx.x];
-    if (oi >= 0) F.results[oi] = st;
+    if (batch) {
+      if (F.b_last) {
+        sb_fit_out r;
+        r.t0 = q[0];
+        r.x0 = (free_mask & SB_FREE_X0) ? expf(q[1]) : F.b_x0[f];
+        r.x1 = q[2];
+        r.c = q[3];
+        r.chi2 = chi2;
+        r.status = status;
+        r.iters = iter < 0 ? 0 : iter;
+        r.n_accept = n_acc;
+        F.b_out[f] = r;
+      }
+    } else {
+      const int oi = F.out_idx[f];
+      if (oi >= 0) F.results[oi] = st;
+    }
   }
 }
 
@@ -343,6 +399,21 @@ hipError_t launch_fit(const KModel& m, const KTables& tb, const KFit& f, hipStre
   const size_t lds = lds_layout_bytes<FIT>(m.n_phase, tb.max_pts, tb.jcap, NW);
   if (lds <= (size_t)tb.lds_limit) return launch_fit_nw<NW>(m, tb, f, lds, st);
   return launch_fit_nw<1>(m, tb, f, fit_lds_bytes(m, tb.max_pts, tb.jcap), st);
+}
+
+hipError_t launch_fit_batch(const KModel& m, const KTables& tb, KFit f, int n_fit, int fit_iters, int iters_per_tick,
+                            hipStream_t st) {
+  const int n_launch = fit_iters <= 0 ? 1 : (fit_iters + iters_per_tick - 1) / iters_per_tick;
+  f.n_active = n_fit;
+  f.fit_iters = fit_iters;
+  f.iters = iters_per_tick;
+  for (int l = 0; l < n_launch; ++l) {
+    f.b_first = l == 0;
+    f.b_last = l == n_launch - 1;
+    const hipError_t e = launch_fit(m, tb, f, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace sbk

@@ -356,6 +356,52 @@ sb_status sb_bandflux_vjp(sb_ctx* ctx, const sb_batch* b, const float* cot, floa
   return launch(ctx, true, kb, (hipStream_t)hip_stream);
 }
 
+static sb_status check_fit_batch(const sb_ctx* ctx, const sb_fit_batch_desc* b, const void* out, const char* who) {
+  const std::string w(who);
+  if (!ctx || !b) return set_error(SB_ERR_ARG, w + ": NULL argument");
+  if (b->n_fit < 0 || b->n_obs < 0) return set_error(SB_ERR_ARG, w + ": negative size");
+  if (b->n_fit > (1 << 24) - 1) return set_error(SB_ERR_ARG, w + ": more than 2^24 - 1 fits in one call");
+  if (ctx->n_bands == 0) return set_error(SB_ERR_STATE, w + ": no band registered");
+  if (b->n_fit > 0 && (!b->z || !b->t0 || !b->x0 || !b->x1 || !b->c || !b->fit_offsets || !out))
+    return set_error(SB_ERR_ARG, w + ": NULL parameter, offset or output array");
+  if (b->n_obs > 0 && (!b->t || !b->band || !b->data || !b->inv_sigma2))
+    return set_error(SB_ERR_ARG, w + ": NULL observation array");
+  return SB_OK;
+}
+
+// The fit kernel's arguments for a batch call (state in `slots`).
+static sbk::KFit make_kfit_batch(sb_ctx* ctx, const sb_fit_batch_desc* b, sb_fit_out* out, sbk::FitSlot* slots) {
+  sbk::KFit f{};
+  f.slots = slots;
+  f.lambda0 = (float)ctx->cfg.lm_lambda0;
+  f.err = ctx->d_err;
+  f.b_off = b->fit_offsets;
+  f.b_z = b->z; f.b_t0 = b->t0; f.b_x0 = b->x0; f.b_x1 = b->x1; f.b_c = b->c;
+  f.b_free = b->free_mask;
+  f.b_t = b->t; f.b_band = b->band; f.b_data = b->data; f.b_w = b->inv_sigma2;
+  f.b_n_obs = b->n_obs;
+  f.b_out = out;
+  return f;
+}
+
+sb_status sb_fit_batch(sb_ctx* ctx, const sb_fit_batch_desc* b, sb_fit_out* out, void* hip_stream) {
+  sb_status st = check_fit_batch(ctx, b, out, "sb_fit_batch");
+  if (st != SB_OK || b->n_fit == 0) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  // per-fit state between the launches: stream-ordered, so it lives exactly as long as the call's work
+  sbk::FitSlot* slots = nullptr;
+  e = hipMallocAsync((void**)&slots, (size_t)b->n_fit * sizeof(sbk::FitSlot), s);
+  if (e != hipSuccess) return set_error(SB_ERR_NOMEM, std::string("sb_fit_batch: hipMallocAsync: ") + hipGetErrorString(e));
+  e = sbk::launch_fit_batch(ctx->km, ctx->tables(), make_kfit_batch(ctx, b, out, slots), b->n_fit, ctx->cfg.fit_iters,
+                            ctx->cfg.iters_per_tick, s);
+  const hipError_t ef = hipFreeAsync(slots, s);
+  if (e != hipSuccess) return hip_fail(e, "sb_fit_batch: launch");
+  if (ef != hipSuccess) return hip_fail(ef, "sb_fit_batch: hipFreeAsync");
+  return SB_OK;
+}
+
 sb_status sb_device_check(sb_ctx* ctx, void* hip_stream) {
   if (!ctx) return set_error(SB_ERR_ARG, "sb_device_check: NULL context");
   hipError_t e = hipSetDevice(ctx->device);

@@ -114,9 +114,27 @@ struct KFit {
   float* data;
   float* w;            // 1/sigma^2
   int* err;
+  // batch mode (sb_fit_batch): fit f is workgroup f and slot f; its observations are the
+  // caller's CSR range; the first launch starts from the caller's arrays, the last one
+  // writes the caller's results
+  const int* b_off;    // non-null: batch mode
+  const float *b_z, *b_t0, *b_x0, *b_x1, *b_c;
+  const unsigned* b_free;
+  const float* b_t;
+  const int* b_band;
+  const float* b_data;
+  const float* b_w;
+  int b_n_obs;
+  int b_first, b_last;
+  sb_fit_out* b_out;
 };
 
 hipError_t launch_fit(const KModel& m, const KTables& tb, const KFit& f, hipStream_t st);
+
+// Batch fits: the fit kernel over n_fit fits in launches of iters_per_tick iterations, state in
+// slots ([n_fit] device FitSlot).
+hipError_t launch_fit_batch(const KModel& m, const KTables& tb, KFit f, int n_fit, int fit_iters,
+                            int iters_per_tick, hipStream_t st);
 size_t fit_lds_bytes(const KModel& m, int max_pts, int jcap);   // smallest form, as lds_bytes
 
 }  // namespace sbk

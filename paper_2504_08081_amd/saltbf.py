@@ -27,7 +27,7 @@ SB_MAX_BANDS, SB_MAX_BAND_POINTS, SB_N_PARAMS = 64, 2048, 5
 EXPORTED = (
     "sb_config_default", "sb_create", "sb_destroy", "sb_add_band", "sb_band_grid", "sb_bandflux",
     "sb_bandflux_vjp", "sb_device_check", "sb_fit_submit", "sb_fit_poll", "sb_fit_wait", "sb_fit_cancel",
-    "sb_stats", "sb_status_string", "sb_last_error",
+    "sb_stats", "sb_status_string", "sb_last_error", "sb_fit_batch",
 )
 
 _f32p = ctypes.POINTER(ctypes.c_float)
@@ -75,6 +75,24 @@ class FitResult(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FitBatchDesc(ctypes.Structure):
+    _fields_ = [("n_fit", ctypes.c_int32), ("n_obs", ctypes.c_int32),
+                ("z", ctypes.c_void_p), ("t0", ctypes.c_void_p), ("x0", ctypes.c_void_p),
+                ("x1", ctypes.c_void_p), ("c", ctypes.c_void_p), ("free_mask", ctypes.c_void_p),
+                ("t", ctypes.c_void_p), ("band", ctypes.c_void_p), ("fit_offsets", ctypes.c_void_p),
+                ("data", ctypes.c_void_p), ("inv_sigma2", ctypes.c_void_p)]
+
+
+class FitOut(ctypes.Structure):
+    """sb_fit_out: one batch fit's result (8 x 4 bytes; a device array of these is a float32/int32 view)."""
+    _fields_ = [("t0", ctypes.c_float), ("x0", ctypes.c_float), ("x1", ctypes.c_float), ("c", ctypes.c_float),
+                ("chi2", ctypes.c_float), ("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("n_accept", ctypes.c_int32)]
+
+
+FIT_OUT_WORDS = 8
 
 
 class Stats(ctypes.Structure):
@@ -133,6 +151,8 @@ def lib():
         L.sb_fit_wait.restype = st
         L.sb_fit_cancel.argtypes = [vp, ctypes.c_uint64]
         L.sb_fit_cancel.restype = st
+        L.sb_fit_batch.argtypes = [vp, ctypes.POINTER(FitBatchDesc), vp, vp]
+        L.sb_fit_batch.restype = st
         L.sb_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.sb_stats.restype = st
         L.sb_status_string.argtypes = [st]
@@ -185,6 +205,18 @@ def _dev(x, dtype, name):
 
 def _ptr(x):
     return None if x is None else ctypes.c_void_p(x.data_ptr())
+
+
+def _grad_buffer(grad, n_sn, device):
+    """The gradient output [n_sn, 5] of an adjoint call: a new tensor, or the caller's, which must be a
+    contiguous float32 device tensor of n_sn * 5 elements (the kernel writes that many floats)."""
+    import torch
+    if grad is None:
+        return torch.empty((n_sn, SB_N_PARAMS), dtype=torch.float32, device=device)
+    _dev(grad, torch.float32, "grad")
+    if grad.numel() != n_sn * SB_N_PARAMS:
+        raise ValueError("grad must have n_sn * 5 elements")
+    return grad
 
 
 def _stream(stream):
@@ -305,8 +337,7 @@ class Context:
         import torch
         b = self._batch(z, t0, x0, x1, c, t, band, sn_offsets, broadcast, data, inv_sigma2, chi2)
         dev = z.device
-        if grad is None:
-            grad = torch.empty((b.n_sn, SB_N_PARAMS), dtype=torch.float32, device=dev)
+        grad = _grad_buffer(grad, b.n_sn, dev)
         nrow = b.n_sn * b.n_obs if broadcast else b.n_obs
         flux = torch.empty(nrow, dtype=torch.float32, device=dev) if want_flux else None
         jac = torch.empty((nrow, SB_N_PARAMS), dtype=torch.float32, device=dev) if want_jac else None
@@ -343,11 +374,7 @@ class Context:
         import torch
         b = self._batch(z, t0, x0, x1, c, t, band, sn_offsets, broadcast, data, inv_sigma2, chi2)
         dev = z.device
-        if grad is None:
-            grad = torch.empty((b.n_sn, SB_N_PARAMS), dtype=torch.float32, device=dev)
-        _dev(grad, torch.float32, "grad")
-        if grad.numel() != b.n_sn * SB_N_PARAMS:
-            raise ValueError("grad must have n_sn * 5 elements")
+        grad = _grad_buffer(grad, b.n_sn, dev)
         nrow = b.n_sn * b.n_obs if broadcast else b.n_obs
         flux = torch.empty(nrow, dtype=torch.float32, device=dev) if want_flux else None
         jac = torch.empty((nrow, SB_N_PARAMS), dtype=torch.float32, device=dev) if want_jac else None
@@ -392,10 +419,61 @@ class Context:
     def fit_cancel(self, ticket):
         _check(lib().sb_fit_cancel(self._h, ticket), "sb_fit_cancel")
 
+    # ------------------------------------------------------------------ batch fits
+    def _fit_batch_desc(self, z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask):
+        import torch
+        for n, v in (("z", z), ("t0", t0), ("x0", x0), ("x1", x1), ("c", c), ("t", t), ("data", data),
+                     ("inv_sigma2", inv_sigma2)):
+            _dev(v, torch.float32, n)
+        _dev(band, torch.int32, "band")
+        _dev(fit_offsets, torch.int32, "fit_offsets")
+        n_fit, n_obs = z.numel(), t.numel()
+        for n, v in (("t0", t0), ("x0", x0), ("x1", x1), ("c", c)):
+            if v.numel() != n_fit:
+                raise ValueError(f"{n} must have n_fit elements")
+        for n, v in (("band", band), ("data", data), ("inv_sigma2", inv_sigma2)):
+            if v.numel() != n_obs:
+                raise ValueError(f"{n} must have n_obs elements")
+        if fit_offsets.numel() != n_fit + 1:
+            raise ValueError("fit_offsets must have n_fit + 1 elements")
+        if free_mask is not None:
+            _dev(free_mask, torch.int32, "free_mask")
+            if free_mask.numel() != n_fit:
+                raise ValueError("free_mask must have n_fit elements")
+        return FitBatchDesc(n_fit, n_obs, _ptr(z), _ptr(t0), _ptr(x0), _ptr(x1), _ptr(c), _ptr(free_mask),
+                            _ptr(t), _ptr(band), _ptr(fit_offsets), _ptr(data), _ptr(inv_sigma2))
+
+    @staticmethod
+    def _fit_out_buffer(out, n_fit, device):
+        import torch
+        if out is None:
+            return torch.empty((n_fit, FIT_OUT_WORDS), dtype=torch.int32, device=device)
+        _dev(out, torch.int32, "out")
+        if out.numel() != n_fit * FIT_OUT_WORDS:
+            raise ValueError("out must hold n_fit sb_fit_out records (8 int32 words each)")
+        return out
+
+    def fit_batch(self, z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask=None, out=None,
+                  stream=None):
+        """Fits every light curve of a device-resident batch (sb_fit_batch).  Returns the raw result
+        records as an int32 tensor [n_fit, 8]; fit_results() unpacks them."""
+        d = self._fit_batch_desc(z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask)
+        out = self._fit_out_buffer(out, d.n_fit, z.device)
+        _check(lib().sb_fit_batch(self._h, ctypes.byref(d), _ptr(out), _stream(stream)), "sb_fit_batch")
+        return out
+
     def stats(self):
         s = Stats()
         _check(lib().sb_stats(self._h, ctypes.byref(s)), "sb_stats")
         return s.as_dict()
+
+
+def fit_results(out):
+    """Unpack sb_fit_out records ([n_fit, 8] int32 tensor or array) into a dict of numpy arrays."""
+    a = np.ascontiguousarray(out.cpu().numpy() if hasattr(out, "cpu") else out, dtype=np.int32).reshape(-1, 8)
+    f = a.view(np.float32)
+    return {"t0": f[:, 0].copy(), "x0": f[:, 1].copy(), "x1": f[:, 2].copy(), "c": f[:, 3].copy(),
+            "chi2": f[:, 4].copy(), "status": a[:, 5].copy(), "iters": a[:, 6].copy(), "n_accept": a[:, 7].copy()}
 
 
 def _saltbandflux_function():

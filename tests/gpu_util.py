@@ -83,42 +83,31 @@ def grad_norm_err(g_gpu, g64, x0):
 U32 = 2.0 ** -24
 
 
-def grad_cond_excess(g_gpu, g64, x0, cot, J64, offsets, c=8.0):
-    """Component error of sum_i cot_i J_i over the FP32 conditioning bound c*u*sum_i |cot_i| max_q |J~_iq|
-    (each Jacobian row carries a few ulp of its largest scaled entry); values <= 1 pass."""
+def grad_propagated_excess(g_gpu, g64, x0, offsets, cot64, J64, J_gpu, cot_err=None, c=4.0):
+    """Component error of a gradient g_q = sum_i cot_i J_iq over the error that the MEASURED errors
+    of its inputs propagate into it, plus the rounding of the FP32 sum itself:
+        B_q = sum_i |dcot_i| |J~_iq| + sum_i |cot_i| |J~_gpu,iq - J~_64,iq| + c u sum_i |cot_i J~_iq|
+    on scaled parameters, with dcot_i the cotangent's own error (0 for a cotangent given exactly;
+    2 w_i |f_gpu,i - f_64,i| for a chi-square cotangent 2 (f_i - d_i) w_i formed from the GPU flux).
+    Each Jacobian row and flux is held to its own bound elsewhere; this checks that the gradient
+    adds no error beyond what those rows and fluxes carry.  Values <= 1 pass."""
     sc = PARAM_SCALE[None, :] * np.ones((len(x0), 1))
     sc[:, 2] = np.asarray(x0, np.float64)
     n_s = np.diff(offsets)
     sc_obs = np.repeat(sc, n_s, axis=0)
-    row = np.abs(np.asarray(J64, np.float64) * sc_obs).max(axis=1)
-    mag = np.zeros(len(x0))
-    for s in range(len(x0)):
-        lo, hi = int(offsets[s]), int(offsets[s + 1])
-        mag[s] = np.sum(np.abs(np.asarray(cot, np.float64)[lo:hi]) * row[lo:hi])
-    err = np.abs((np.asarray(g_gpu, np.float64) - np.asarray(g64, np.float64)) * sc)
-    return err / np.maximum(c * U32 * mag[:, None], 1e-300)
+    Jt = np.asarray(J64, np.float64) * sc_obs
+    dJ = np.abs(np.asarray(J_gpu, np.float64) * sc_obs - Jt)
+    cot = np.abs(np.asarray(cot64, np.float64))
+    dc = np.zeros_like(cot) if cot_err is None else np.abs(np.asarray(cot_err, np.float64))
+    off = np.asarray(offsets, np.int64)
 
+    def seg(v):   # per-supernova sums of the rows of v
+        cs = np.vstack([np.zeros((1, v.shape[1])), np.cumsum(v, axis=0)])
+        return cs[off[1:]] - cs[off[:-1]]
 
-def chi2_grad_propagated_excess(g_gpu, g64, x0, f64, data, w, J64, offsets, flux_tol=FLUX_TOL, c=8.0):
-    """Component error of a chi-square gradient over the error that fluxes within flux_tol propagate
-    into it: the cotangent 2 (f - d) w carries 2 w |delta f| <= 2 w flux_tol |f|, so component q
-    may be off by sum_i 2 w_i flux_tol |f_i| |J~_iq|, plus the FP32 arithmetic term of
-    grad_cond_excess.  Values <= 1 pass."""
-    sc = PARAM_SCALE[None, :] * np.ones((len(x0), 1))
-    sc[:, 2] = np.asarray(x0, np.float64)
-    n_s = np.diff(offsets)
-    Jt = np.abs(np.asarray(J64, np.float64) * np.repeat(sc, n_s, axis=0))
-    f = np.asarray(f64, np.float64)
-    ww = np.asarray(w, np.float64)
-    cot = 2.0 * (f - np.asarray(data, np.float64)) * ww
-    prop = np.zeros((len(x0), 5))
-    mag = np.zeros(len(x0))
-    for s in range(len(x0)):
-        lo, hi = int(offsets[s]), int(offsets[s + 1])
-        prop[s] = (2.0 * ww[lo:hi] * flux_tol * np.abs(f[lo:hi]))[:, None].T @ Jt[lo:hi]
-        mag[s] = np.sum(np.abs(cot[lo:hi]) * Jt[lo:hi].max(axis=1))
+    bound = seg(dc[:, None] * np.abs(Jt)) + seg(cot[:, None] * dJ) + c * U32 * seg(cot[:, None] * np.abs(Jt))
     err = np.abs((np.asarray(g_gpu, np.float64) - np.asarray(g64, np.float64)) * sc)
-    return err / np.maximum(prop + c * U32 * mag[:, None], 1e-300)
+    return err / np.maximum(bound, 1e-300)
 
 
 # ----------------------------------------------------------------------------- the oracle over a whole batch

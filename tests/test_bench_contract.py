@@ -1,5 +1,6 @@
 """CPU checks of bench.py's bookkeeping: the committed rocprofv3 summary belongs to the current
-device code (so `roofline.traffic` is reported), and the code hash ignores comments only."""
+device code (so `roofline.traffic` and the executed flops behind `roofline.achieved` are reported),
+and the code hash ignores comments only."""
 import importlib.util
 import os
 
@@ -15,9 +16,10 @@ def _bench():
 
 def test_committed_profile_matches_the_device_code():
     b = _bench()
-    traffic = b.profiled_traffic(b.PROFILE_VJP)
-    assert traffic is not None, "device code changed since profiles/ was recorded: profile again"
-    assert 1e6 < traffic < 1e9
+    rec = b.profile_record(b.PROFILE_VJP)
+    assert rec, "device code changed since profiles/ was recorded: profile again"
+    assert 1e6 < rec["traffic"] < 1e9
+    assert 1e8 < rec["executed_flops"] < 1e11
 
 
 def test_code_hash_ignores_comments_and_blank_lines_only():

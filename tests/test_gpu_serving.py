@@ -13,6 +13,15 @@ from gpu_util import torch_or_skip
 
 pytestmark = pytest.mark.gpu
 
+# GPU fit against the FP64 LM fit from the same start.  The minimum chi-square is held to 1e-5
+# relative.  The parameters are held to 1e-2 of their statistical uncertainty sigma_q: an FP32 fit
+# accepts a step only when its FP32 chi-square is lower, and near the minimum a step of
+# delta sigma_q lowers chi2 by about delta^2, so steps below sqrt(eps chi2) sigma_q (eps ~ 1e-6, the
+# FP32 chi-square's relative error; chi2 ~ 10-300) cannot be told apart from rounding: the FP32
+# optimum is fixed to a few 1e-3 sigma_q, not to 1e-4.
+CHI2_TOL = 1e-5
+THETA_SIGMA_TOL = 1e-2
+
 
 @pytest.fixture(scope="module")
 def torch():
@@ -68,7 +77,7 @@ def run_all(ctx, items, timeout=60.0):
 
 def test_fits_match_oracle(sb, o6, model, bands6, requests):
     """Every GPU fit of 40 requests against the FP64 LM fit from the same start: parameters within
-    1e-2 of their statistical uncertainty, chi2 within 1e-4."""
+    1e-2 of their statistical uncertainty, minimum chi2 within 1e-5."""
     ctx = sb.Context.from_model(model, bands6)
     items = requests
     res = run_all(ctx, items)
@@ -84,8 +93,8 @@ def test_fits_match_oracle(sb, o6, model, bands6, requests):
         sig_q = np.sqrt(np.diag(np.linalg.inv(H)))
         dev = np.abs(qg - q64) / sig_q
         worst = max(worst, dev.max())
-        assert dev.max() <= 1e-2, (dev, g.as_dict(), ref)
-        assert abs(g.chi2 - ref["chi2"]) <= 1e-4 * ref["chi2"]
+        assert dev.max() <= THETA_SIGMA_TOL, (dev, g.as_dict(), ref)
+        assert abs(g.chi2 - ref["chi2"]) <= CHI2_TOL * ref["chi2"]
     print(f"fit parity: max |dq|/sigma_q = {worst:.2e}")
     ctx.close()
 
@@ -93,7 +102,7 @@ def test_fits_match_oracle(sb, o6, model, bands6, requests):
 @pytest.mark.parametrize("mask", [7, 13, 11])
 def test_fits_with_held_parameters(sb, o6, model, bands6, requests, mask):
     """free_mask: the held parameters come back exactly as submitted, and the free ones match the
-    FP64 LM fit over the same subset (within 1e-2 of their uncertainty, chi2 within 1e-4).  The
+    FP64 LM fit over the same subset (within 1e-2 of their uncertainty, chi2 within 1e-5).  The
     fits share launches with all-free fits of the same requests."""
     ctx = sb.Context.from_model(model, bands6)
     items = requests[12:20]
@@ -121,8 +130,8 @@ def test_fits_with_held_parameters(sb, o6, model, bands6, requests, mask):
         sig_q = np.sqrt(np.diag(np.linalg.inv(H[np.ix_(fr, fr)])))
         dev = np.abs(qg[fr] - q64[fr]) / sig_q
         worst = max(worst, dev.max())
-        assert dev.max() <= 1e-2, (dev, g.as_dict(), ref)
-        assert abs(g.chi2 - ref["chi2"]) <= 1e-4 * ref["chi2"]
+        assert dev.max() <= THETA_SIGMA_TOL, (dev, g.as_dict(), ref)
+        assert abs(g.chi2 - ref["chi2"]) <= CHI2_TOL * ref["chi2"]
         assert g.chi2 >= ga.chi2 * (1 - 1e-5)   # holding parameters cannot fit better
     print(f"free_mask {mask}: max |dq|/sigma_q = {worst:.2e}")
     with pytest.raises(sb.SaltBFError):
@@ -145,8 +154,8 @@ def test_fits_with_single_wave_workgroups(sb, o6, model, bands6, requests):
         qg = np.array([g.t0, np.log(g.x0), g.x1, g.c])
         _, H, _ = fo.evaluate(single_batch(r), r.z, q64, d, w)
         sig_q = np.sqrt(np.diag(np.linalg.inv(H)))
-        assert (np.abs(qg - q64) / sig_q).max() <= 1e-2
-        assert abs(g.chi2 - ref["chi2"]) <= 1e-4 * ref["chi2"]
+        assert (np.abs(qg - q64) / sig_q).max() <= THETA_SIGMA_TOL
+        assert abs(g.chi2 - ref["chi2"]) <= CHI2_TOL * ref["chi2"]
     ctx.close()
 
 
@@ -166,6 +175,30 @@ def test_alone_vs_in_the_mix_bitwise(sb, o6, model, bands6):
     st = ctx.stats()
     assert st["completed"] == 200 and st["queue_depth"] == 0 and st["active_slots"] == 0
     assert st["slot_ticks"] > st["ticks"]   # the mixed fits did share launches
+    ctx.close()
+
+
+def test_diverged_request_is_isolated(sb, model, bands6, requests):
+    """A request whose start overflows the flux (x0 = 1e30: every model flux is beyond FP32 range,
+    so its chi-square at the start is not finite) ends as SB_FIT_DIVERGED after no iteration, and
+    only that ticket: the twelve fits sharing its launches are bitwise their results alone."""
+    ctx = sb.Context.from_model(model, bands6)
+    items = requests[:12]
+    alone = [run_all(ctx, [it])[0] for it in items]
+    r, d, sig, _ = requests[20]
+    tks = [submit(ctx, it) for it in items[:6]]
+    bad = ctx.fit_submit(r.t, r.band, d, sig, r.z, r.theta_init[0], 1e30, r.theta_init[2], r.theta_init[3])
+    tks += [submit(ctx, it) for it in items[6:]]
+    res = [ctx.fit_wait(tk, 60.0) for tk in tks]
+    rb = ctx.fit_wait(bad, 60.0)
+    assert rb is not None and rb.status == sb.SB_FIT_DIVERGED and rb.iters == 0
+    assert not np.isfinite(rb.chi2)
+    for i, (a, m) in enumerate(zip(alone, res)):
+        assert m is not None and m.status == sb.SB_OK
+        assert result_key(m) == result_key(a), i
+    st = ctx.stats()
+    assert st["completed"] == 25 and st["active_slots"] == 0
+    ctx.device_check()
     ctx.close()
 
 
