@@ -269,6 +269,17 @@ typedef struct {
  * pointers or sizes; n_fit = 0 does nothing. */
 sb_status sb_fit_batch(sb_ctx *ctx, const sb_fit_batch_desc *batch, sb_fit_out *out, void *hip_stream);
 
+/* The same batch fit for callers that cannot allocate (code under HIP graph
+ * capture, serving loops that must not call hipMalloc): identical results to
+ * sb_fit_batch, with the per-fit state in a fixed device array that the library
+ * holds on each GPU it runs on until the process ends (SB_FIT_NOALLOC_MAX fits,
+ * about 128 bytes each).  It calls no allocation routine.  n_fit above
+ * SB_FIT_NOALLOC_MAX is SB_ERR_ARG.  Every call on one GPU uses the same array:
+ * calls whose work overlaps on a GPU (different streams, or different contexts
+ * on the same device) race and must be serialised by the caller. */
+#define SB_FIT_NOALLOC_MAX 8192
+sb_status sb_fit_batch_noalloc(sb_ctx *ctx, const sb_fit_batch_desc *batch, sb_fit_out *out, void *hip_stream);
+
 typedef struct {
   int64_t submitted, admitted, completed, cancelled, rejected;
   int64_t ticks;               /* server launches */

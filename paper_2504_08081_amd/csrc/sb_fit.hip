@@ -12,6 +12,7 @@
 // fit gives the same result however its iterations are split over launches and
 // whichever other fits share the launch.
 #include <climits>
+#include <mutex>
 
 #include "sb_device.h"
 
@@ -399,6 +400,38 @@ hipError_t launch_fit(const KModel& m, const KTables& tb, const KFit& f, hipStre
   const size_t lds = lds_layout_bytes<FIT>(m.n_phase, tb.max_pts, tb.jcap, NW);
   if (lds <= (size_t)tb.lds_limit) return launch_fit_nw<NW>(m, tb, f, lds, st);
   return launch_fit_nw<1>(m, tb, f, fit_lds_bytes(m, tb.max_pts, tb.jcap), st);
+}
+
+// ------------------------------------------------------------ allocation-free batch fits
+//
+// The per-fit state of sb_fit_batch_noalloc lives in this fixed device array
+// (one copy per GPU, held until the process ends).  Host code never passes the
+// array's name to a kernel: the name is a host-side stand-in, and the device
+// address comes from hipGetSymbolAddress, taken once per device at context
+// creation with that device current.
+static __device__ __align__(256) FitSlot scratch[SB_FIT_NOALLOC_MAX];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+FitSlot* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t fit_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = (FitSlot*)p;
+  return hipSuccess;
+}
+
+FitSlot* fit_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 hipError_t launch_fit_batch(const KModel& m, const KTables& tb, KFit f, int n_fit, int fit_iters, int iters_per_tick,

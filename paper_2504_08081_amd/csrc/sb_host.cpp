@@ -174,6 +174,10 @@ sb_status sb_create(const sb_model_desc* md, const sb_config* cfg_in, int device
   e = hipGetDeviceProperties(&prop, device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
 
+  // the device address of the allocation-free fits' state array, once per device
+  e = sbk::fit_scratch_init(device);
+  if (e != hipSuccess) return hip_fail(e, "sb_create: hipGetSymbolAddress of the fit state array");
+
   sb_ctx* c = new (std::nothrow) sb_ctx();
   if (!c) return set_error(SB_ERR_NOMEM, "sb_create: host allocation");
   c->device = device;
@@ -399,6 +403,23 @@ sb_status sb_fit_batch(sb_ctx* ctx, const sb_fit_batch_desc* b, sb_fit_out* out,
   const hipError_t ef = hipFreeAsync(slots, s);
   if (e != hipSuccess) return hip_fail(e, "sb_fit_batch: launch");
   if (ef != hipSuccess) return hip_fail(ef, "sb_fit_batch: hipFreeAsync");
+  return SB_OK;
+}
+
+sb_status sb_fit_batch_noalloc(sb_ctx* ctx, const sb_fit_batch_desc* b, sb_fit_out* out, void* hip_stream) {
+  sb_status st = check_fit_batch(ctx, b, out, "sb_fit_batch_noalloc");
+  if (st != SB_OK || b->n_fit == 0) return st;
+  if (b->n_fit > SB_FIT_NOALLOC_MAX)
+    return set_error(SB_ERR_ARG, "sb_fit_batch_noalloc: n_fit exceeds SB_FIT_NOALLOC_MAX (" +
+                                     std::to_string(SB_FIT_NOALLOC_MAX) + "); split the batch or use sb_fit_batch");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  sbk::FitSlot* slots = sbk::fit_scratch(ctx->device);
+  if (!slots) return set_error(SB_ERR_STATE, "sb_fit_batch_noalloc: no state array for this device");
+  // every slot the call uses is written by its first launch before any launch reads it
+  e = sbk::launch_fit_batch(ctx->km, ctx->tables(), make_kfit_batch(ctx, b, out, slots), b->n_fit,
+                            ctx->cfg.fit_iters, ctx->cfg.iters_per_tick, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "sb_fit_batch_noalloc: launch");
   return SB_OK;
 }
 

@@ -137,4 +137,10 @@ hipError_t launch_fit_batch(const KModel& m, const KTables& tb, KFit f, int n_fi
                             int iters_per_tick, hipStream_t st);
 size_t fit_lds_bytes(const KModel& m, int max_pts, int jcap);   // smallest form, as lds_bytes
 
+// The fixed per-device state array of allocation-free batch fits
+// (SB_FIT_NOALLOC_MAX slots): fit_scratch_init takes its device address once per
+// device (that device current); fit_scratch returns it, or null before.
+hipError_t fit_scratch_init(int device);
+FitSlot* fit_scratch(int device);
+
 }  // namespace sbk

@@ -23,11 +23,12 @@ SB_OBS_BROADCAST, SB_OUT_CHI2 = 1, 2
 SB_QUAD_TRAPEZOID, SB_QUAD_MIDPOINT = 0, 1
 SB_FREE_T0, SB_FREE_X0, SB_FREE_X1, SB_FREE_C, SB_FREE_ALL = 1, 2, 4, 8, 15
 SB_MAX_BANDS, SB_MAX_BAND_POINTS, SB_N_PARAMS = 64, 2048, 5
+SB_FIT_NOALLOC_MAX = 8192
 
 EXPORTED = (
     "sb_config_default", "sb_create", "sb_destroy", "sb_add_band", "sb_band_grid", "sb_bandflux",
     "sb_bandflux_vjp", "sb_device_check", "sb_fit_submit", "sb_fit_poll", "sb_fit_wait", "sb_fit_cancel",
-    "sb_stats", "sb_status_string", "sb_last_error", "sb_fit_batch",
+    "sb_stats", "sb_status_string", "sb_last_error", "sb_fit_batch", "sb_fit_batch_noalloc",
 )
 
 _f32p = ctypes.POINTER(ctypes.c_float)
@@ -153,6 +154,8 @@ def lib():
         L.sb_fit_cancel.restype = st
         L.sb_fit_batch.argtypes = [vp, ctypes.POINTER(FitBatchDesc), vp, vp]
         L.sb_fit_batch.restype = st
+        L.sb_fit_batch_noalloc.argtypes = [vp, ctypes.POINTER(FitBatchDesc), vp, vp]
+        L.sb_fit_batch_noalloc.restype = st
         L.sb_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.sb_stats.restype = st
         L.sb_status_string.argtypes = [st]
@@ -460,6 +463,16 @@ class Context:
         d = self._fit_batch_desc(z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask)
         out = self._fit_out_buffer(out, d.n_fit, z.device)
         _check(lib().sb_fit_batch(self._h, ctypes.byref(d), _ptr(out), _stream(stream)), "sb_fit_batch")
+        return out
+
+    def fit_batch_noalloc(self, z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask=None, out=None,
+                          stream=None):
+        """As fit_batch, through sb_fit_batch_noalloc (fixed per-device state array, no allocation in
+        the library; at most SB_FIT_NOALLOC_MAX fits; calls overlapping on one GPU race)."""
+        d = self._fit_batch_desc(z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask)
+        out = self._fit_out_buffer(out, d.n_fit, z.device)
+        _check(lib().sb_fit_batch_noalloc(self._h, ctypes.byref(d), _ptr(out), _stream(stream)),
+               "sb_fit_batch_noalloc")
         return out
 
     def stats(self):
