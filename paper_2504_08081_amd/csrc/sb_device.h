@@ -34,6 +34,7 @@ namespace sbk {
 // it, so the compiler keeps those exits uniform and never splits a wave
 // around a barrier.
 __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline float uni_f(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
 
 // Which row projections a pass computes.
 //   FWD: Rx                       (flux)

@@ -15,6 +15,7 @@
 #include <mutex>
 
 #include "sb_device.h"
+#include "sb_lbfgsb.h"
 
 namespace sbk {
 
@@ -25,6 +26,8 @@ struct FitShared {
   int slot_of[SB_MAX_BANDS];
   int slot_ok[BAND_GROUP];
   float red[red_floats(16, MAX_NW)];
+  FitSlot lb;      // L-BFGS-B: the fit's state, updated by thread 0 between evaluations
+  int lb_go;       // L-BFGS-B: thread 0 planned another evaluation
 };
 
 // chi2, H (packed) and g at parameters q = (t0, ln x0, x1, c); every thread gets them.
@@ -197,6 +200,117 @@ __device__ bool damped_solve(const float* H, const float* g, float lambda, int f
   return true;
 }
 
+// Where a fit starts: its observations, redshift, starting point, free mask and
+// (L-BFGS-B) bounds of q, from the admission header or the caller's batch arrays.
+struct FitStart {
+  float z;
+  float q[4];
+  float lo[4], hi[4];
+  int free_mask;
+  bool bad;          // malformed offsets or bounds: nothing to fit
+};
+
+// Bounds of q = (t0, ln x0, x1, c) from bounds of (t0, x0, x1, c) (null: none); an x0 bound
+// <= 0 is no lower bound; false if a bound is NaN, an upper x0 bound is <= 0 or lo > hi.
+__device__ inline bool q_bounds(const float* lower, const float* upper, float* lo, float* hi) {
+  const float inf = __builtin_inff();
+  bool ok = true;
+  for (int i = 0; i < 4; ++i) {
+    float a = lower ? lower[i] : -inf, b = upper ? upper[i] : inf;
+    if (i == 1) {
+      a = a > 0.f ? (float)log((double)a) : -inf;
+      if (upper) {
+        ok = ok && b > 0.f;
+        b = b > 0.f ? (float)log((double)b) : -inf;
+      }
+    }
+    ok = ok && !(a != a) && !(b != b) && a <= b;
+    lo[i] = a;
+    hi[i] = b;
+  }
+  return ok;
+}
+
+// The L-BFGS-B iterations of one fit (sb_lbfgsb.h): thread 0 keeps the state in
+// LDS and plans each evaluation; every thread evaluates chi2 and its gradient
+// at the planned point.
+template <int NW>
+__device__ void fit_lbfgsb(const KModel& m, const KTables& tb, const KFit& F, const FitObs& O, int obs_off,
+                           bool start, const FitStart& fs, FitSlot* sl, int f, const Lds& L, FitShared& S) {
+  const int tid = threadIdx.x;
+  FitSlot& st = S.lb;
+  if (tid == 0) {
+    if (start) {
+      st = FitSlot{};
+      st.obs_off = obs_off;
+      st.n_obs = O.n;
+      st.iter = -1;
+      st.status = SB_OK;
+      st.free_mask = fs.free_mask;
+      st.z = fs.z;
+      for (int i = 0; i < 4; ++i) {
+        const bool fr = (fs.free_mask >> i) & 1;
+        st.lb_lo[i] = fr ? fs.lo[i] : fs.q[i];
+        st.lb_hi[i] = fr ? fs.hi[i] : fs.q[i];
+        st.q[i] = fminf(fmaxf(fs.q[i], st.lb_lo[i]), st.lb_hi[i]);
+      }
+      st.lb_phase = LB_NEED_DIR;
+      st.lb_first = 1;
+      if (fs.bad) {
+        st.chi2 = __builtin_nanf("");
+        st.iter = 0;
+        st.status = SB_FIT_DIVERGED;
+      }
+    } else {
+      st = *sl;
+    }
+  }
+  __syncthreads();
+  const double s64 = 1.0 / (1.0 + (double)uni_f(S.lb.z));
+  float out[15];
+  if (uni(S.lb.iter < 0 ? 1 : 0)) {
+    float q[4] = {S.lb.q[0], S.lb.q[1], S.lb.q[2], S.lb.q[3]};
+    fit_eval<NW>(m, tb, F, O, s64, q, L, S, out);
+    if (tid == 0) {
+      st.chi2 = out[14];
+      if (isfinite(out[14])) {
+        for (int i = 0; i < 4; ++i) st.g[i] = out[10 + i];
+        st.iter = 0;
+      } else {
+        st.status = SB_FIT_DIVERGED;
+      }
+    }
+  }
+  for (int it = 0; it < F.iters; ++it) {
+    if (tid == 0) S.lb_go = lb_plan(st, F.fit_iters) ? 1 : 0;
+    __syncthreads();
+    if (!uni(S.lb_go)) break;
+    float q[4] = {S.lb.lb_trial[0], S.lb.lb_trial[1], S.lb.lb_trial[2], S.lb.lb_trial[3]};
+    fit_eval<NW>(m, tb, F, O, s64, q, L, S, out);
+    if (tid == 0) lb_after_eval(st, out[14], out + 10, F.lbfgs_m);
+  }
+  if (tid == 0) {
+    *sl = st;
+    if (F.b_off) {
+      if (F.b_last) {
+        sb_fit_out r;
+        r.t0 = st.q[0];
+        r.x0 = (st.free_mask & SB_FREE_X0) ? expf(st.q[1]) : F.b_x0[f];
+        r.x1 = st.q[2];
+        r.c = st.q[3];
+        r.chi2 = st.chi2;
+        r.status = st.status;
+        r.iters = st.iter < 0 ? 0 : st.iter;
+        r.n_accept = st.n_accept;
+        F.b_out[f] = r;
+      }
+    } else {
+      const int oi = F.out_idx[f];
+      if (oi >= 0) F.results[oi] = st;
+    }
+  }
+}
+
 template <int NW>
 __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F) {
   constexpr int NT = NW * WAVE;
@@ -210,19 +324,16 @@ __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F)
   const int f = blockIdx.x;
   FitSlot* sl = F.slots + (batch ? f : F.active[f]);
   const int adm = batch ? -1 : uni(F.admit[f]);
-  FitObs O;
-  float z;
-  // the LM state; every thread holds the same values
-  float q[4], H[10], g[4], lambda, chi2;
-  int iter, n_acc, status, free_mask, obs_off = 0;
-  bool bad_csr = false;
   const bool start = batch ? (F.b_first != 0) : (adm >= 0);
+  FitObs O;
+  int obs_off = 0;
+  FitStart fs{};
   if (start) {
     if (batch) {
       // first launch of a batch fit: its observations are the caller's CSR range
       int lo = F.b_off[f], hi = F.b_off[f + 1];
-      bad_csr = lo < 0 || hi < lo || hi > F.b_n_obs;
-      if (bad_csr) {
+      fs.bad = lo < 0 || hi < lo || hi > F.b_n_obs;
+      if (fs.bad) {
         if (tid == 0) atomicOr(F.err, EFLAG_CSR);
         lo = hi = 0;
       }
@@ -232,13 +343,15 @@ __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F)
       O.w = F.b_w + lo;
       O.n = hi - lo;
       obs_off = lo;
-      z = F.b_z[f];
-      q[0] = F.b_t0[f];
-      q[1] = (float)log((double)F.b_x0[f]);
-      q[2] = F.b_x1[f];
-      q[3] = F.b_c[f];
+      fs.z = F.b_z[f];
+      fs.q[0] = F.b_t0[f];
+      fs.q[1] = (float)log((double)F.b_x0[f]);
+      fs.q[2] = F.b_x1[f];
+      fs.q[3] = F.b_c[f];
       const int fm = F.b_free ? (int)(F.b_free[f] & (unsigned)SB_FREE_ALL) : 0;
-      free_mask = fm == 0 ? SB_FREE_ALL : fm;
+      fs.free_mask = fm == 0 ? SB_FREE_ALL : fm;
+      if (!q_bounds(F.b_lower ? F.b_lower + 4 * f : nullptr, F.b_upper ? F.b_upper + 4 * f : nullptr, fs.lo, fs.hi))
+        fs.bad = true;
     } else {
       // first launch of a served fit: move its observations from the inbox to the arena
       const AdmitHeader h = F.hdr[adm];
@@ -255,13 +368,39 @@ __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F)
       O.w = F.in_w + h.src_off;
       O.n = h.n_obs;
       obs_off = h.arena_off;
-      z = h.z;
-      q[0] = h.t0;
-      q[1] = h.lnx0;
-      q[2] = h.x1;
-      q[3] = h.c;
-      free_mask = h.free_mask;
+      fs.z = h.z;
+      fs.q[0] = h.t0;
+      fs.q[1] = h.lnx0;
+      fs.q[2] = h.x1;
+      fs.q[3] = h.c;
+      fs.free_mask = h.free_mask;
+      for (int i = 0; i < 4; ++i) {
+        fs.lo[i] = h.lo[i];
+        fs.hi[i] = h.hi[i];
+      }
     }
+  } else {
+    obs_off = sl->obs_off;
+    O.t = (batch ? F.b_t : F.t) + obs_off;
+    O.band = (batch ? F.b_band : F.band) + obs_off;
+    O.data = (batch ? F.b_data : F.data) + obs_off;
+    O.w = (batch ? F.b_w : F.w) + obs_off;
+    O.n = sl->n_obs;
+  }
+  if (uni(F.solver) == SB_SOLVER_LBFGSB) {
+    fit_lbfgsb<NW>(m, tb, F, O, obs_off, start, fs, sl, f, L, S);
+    return;
+  }
+
+  // Levenberg-Marquardt: the state in registers; every thread holds the same values
+  float z;
+  float q[4], H[10], g[4], lambda, chi2;
+  int iter, n_acc, status, free_mask;
+  if (start) {
+    z = fs.z;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = fs.q[k];
+    free_mask = fs.free_mask;
 #pragma unroll
     for (int k = 0; k < 10; ++k) H[k] = 0.f;
 #pragma unroll
@@ -271,19 +410,13 @@ __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F)
     iter = -1;
     n_acc = 0;
     status = SB_OK;
-    if (uni(bad_csr ? 1 : 0)) {
+    if (uni(fs.bad ? 1 : 0)) {
       // malformed offsets: no observations to fit
       chi2 = __builtin_nanf("");
       iter = 0;
       status = SB_FIT_DIVERGED;
     }
   } else {
-    obs_off = sl->obs_off;
-    O.t = (batch ? F.b_t : F.t) + obs_off;
-    O.band = (batch ? F.b_band : F.band) + obs_off;
-    O.data = (batch ? F.b_data : F.data) + obs_off;
-    O.w = (batch ? F.b_w : F.w) + obs_off;
-    O.n = sl->n_obs;
     z = sl->z;
 #pragma unroll
     for (int k = 0; k < 4; ++k) q[k] = sl->q[k];
@@ -344,14 +477,13 @@ __global__ __launch_bounds__(NW * WAVE) void k_fit(KModel m, KTables tb, KFit F)
     iter += 1;
   }
   if (tid == 0) {
-    FitSlot st;
+    FitSlot st{};
     st.obs_off = obs_off;
     st.n_obs = O.n;
     st.iter = iter;
     st.n_accept = n_acc;
     st.status = status;
     st.free_mask = free_mask;
-    st.pad_[0] = st.pad_[1] = 0;
     st.z = z;
     for (int k = 0; k < 4; ++k) st.q[k] = q[k];
     st.lambda = lambda;

@@ -65,21 +65,36 @@ hipError_t launch_sn(bool adj, const KModel& m, const KTables& tb, const KBatch&
 
 // ------------------------------------------------------------------ fit server
 
-// Per-fit device state; lives in the server's slot array between launches.
+constexpr int LB_MAX_M = 5;       // L-BFGS-B correction pairs kept, at most
+
+// Per-fit device state; lives in the server's slot array (or the batch fit's
+// scratch) between launches.
 struct FitSlot {
-  int obs_off;      // first observation in the arena
+  int obs_off;      // first observation in the arena (batch fits: in the caller's arrays)
   int n_obs;
-  int iter;         // LM iterations done; -1 = not yet evaluated at the start point
+  int iter;         // iterations (evaluations) done; -1 = not yet evaluated at the start point
   int n_accept;
   int status;       // SB_OK / SB_FIT_DIVERGED
   int free_mask;    // SB_FREE_* bits of the parameters the fit varies
-  int pad_[2];
+  int lb_phase;     // L-BFGS-B: needs a direction / in a line search / done
+  int lb_n;         // L-BFGS-B: correction pairs kept
+  int lb_first;     // L-BFGS-B: first iteration since a (re)start
+  int lb_has_hi;    // L-BFGS-B line search: the bracket has an upper end
+  int lb_trials;    // L-BFGS-B line search: evaluations in the current search
+  int pad_;
   float z;
   float q[4];       // t0, ln x0, x1, c
-  float lambda;
+  float lambda;     // LM damping
   float chi2;
-  float H[10];      // J^T W J, packed upper triangle (00 01 02 03 11 12 13 22 23 33)
-  float g[4];       // J^T W r
+  float H[10];      // LM: J^T W J, packed upper triangle (00 01 02 03 11 12 13 22 23 33)
+  float g[4];       // J^T W r at q (chi2's gradient is -2 g)
+  // L-BFGS-B (solver SB_SOLVER_LBFGSB)
+  float lb_lo[4], lb_hi[4];              // bounds of q
+  float lb_S[LB_MAX_M][4], lb_Y[LB_MAX_M][4];   // correction pairs, oldest first
+  float lb_d[4], lb_trial[4];            // search direction, trial point
+  float lb_gd, lb_a, lb_amax;            // slope along d at q, trial step, largest feasible step
+  float lb_alo, lb_flo, lb_glo;          // best step of the search so far (chi2, slope)
+  float lb_ahi, lb_fhi, lb_ghi;          // other end of the bracket
 };
 
 // A request admitted in this launch: copied from the inbox into its arena range
@@ -92,6 +107,7 @@ struct AdmitHeader {
   float z, t0, lnx0, x1, c;
   int free_mask;
   int pad_[2];
+  float lo[4], hi[4];   // L-BFGS-B bounds of (t0, ln x0, x1, c); +-inf when none
 };
 
 struct KFit {
@@ -108,6 +124,8 @@ struct KFit {
   int n_active;
   int iters;           // iterations to run this launch
   int fit_iters;       // total per fit
+  int solver;          // SB_SOLVER_LM or SB_SOLVER_LBFGSB
+  int lbfgs_m;         // L-BFGS-B correction pairs kept (1..LB_MAX_M)
   float lambda0;
   float* t;            // arena [capacity]: observations of resident fits
   int* band;
@@ -120,6 +138,7 @@ struct KFit {
   const int* b_off;    // non-null: batch mode
   const float *b_z, *b_t0, *b_x0, *b_x1, *b_c;
   const unsigned* b_free;
+  const float *b_lower, *b_upper;   // [n_fit][4] L-BFGS-B bounds of (t0, x0, x1, c), or null
   const float* b_t;
   const int* b_band;
   const float* b_data;

@@ -150,6 +150,25 @@ sb_status Server::submit(const sb_fit_request* r, uint64_t* ticket) {
     if (!std::isfinite(r->t[i]) || !std::isfinite(r->data[i]) || !std::isfinite(r->sigma[i]) || !(r->sigma[i] > 0.f))
       return set_error(SB_ERR_ARG, "sb_fit_submit: non-finite observation or sigma <= 0");
   }
+  // bounds of q = (t0, ln x0, x1, c)
+  float qlo[4], qhi[4];
+  for (int i = 0; i < 4; ++i) {
+    qlo[i] = -INFINITY;
+    qhi[i] = INFINITY;
+  }
+  if (r->has_bounds) {
+    if (cfg.solver != SB_SOLVER_LBFGSB)
+      return set_error(SB_ERR_ARG, "sb_fit_submit: bounds need the L-BFGS-B solver (sb_config.solver)");
+    for (int i = 0; i < 4; ++i) {
+      const float a = r->lower[i], b = r->upper[i];
+      if (std::isnan(a) || std::isnan(b) || !(a <= b)) return set_error(SB_ERR_ARG, "sb_fit_submit: bounds");
+      qlo[i] = a;
+      qhi[i] = b;
+    }
+    if (!(r->upper[1] > 0.f)) return set_error(SB_ERR_ARG, "sb_fit_submit: x0 upper bound must be > 0");
+    qlo[1] = r->lower[1] > 0.f ? (float)std::log((double)r->lower[1]) : -INFINITY;
+    qhi[1] = std::isinf(r->upper[1]) ? INFINITY : (float)std::log((double)r->upper[1]);
+  }
   const int64_t bytes = (int64_t)r->n_obs * 16 + (int64_t)sizeof(sbk::FitSlot);
   if (bytes > cfg.hbm_budget_bytes || r->n_obs > arena_.capacity())
     return set_error(SB_ERR_BUDGET, "sb_fit_submit: request larger than the serving budget");
@@ -168,6 +187,10 @@ sb_status Server::submit(const sb_fit_request* r, uint64_t* ticket) {
   q.x1 = r->x1;
   q.c = r->c;
   q.free_mask = r->free_mask == 0 ? SB_FREE_ALL : (int)r->free_mask;
+  for (int i = 0; i < 4; ++i) {
+    q.lo[i] = qlo[i];
+    q.hi[i] = qhi[i];
+  }
   q.bytes = bytes;
   q.t_submit = now_seconds();
   {
@@ -251,6 +274,7 @@ void Server::stats(sb_stats_t* out) {
   out->budget_bytes = ctx_->cfg.hbm_budget_bytes;
   out->busy_seconds = busy_s_;
   out->slot_ticks = n_slot_ticks_;
+  for (int k = 0; k < SB_LATENCY_BINS; ++k) out->latency_hist[k] = lat_hist_[k];
 }
 
 void Server::release_slot(int s) {
@@ -355,6 +379,10 @@ bool Server::prepare_tick(int parity, std::vector<Retire>& retire, size_t& blob_
     h.x1 = q.x1;
     h.c = q.c;
     h.free_mask = q.free_mask;
+    for (int i = 0; i < 4; ++i) {
+      h.lo[i] = q.lo[i];
+      h.hi[i] = q.hi[i];
+    }
     hdr.push_back(h);
     src += sl.n_obs;
   }
@@ -416,6 +444,11 @@ void Server::finish_tick(int parity) {
           res.iters = st.iter < 0 ? 0 : st.iter;
           res.n_accept = st.n_accept;
           ++n_completed_;
+          // latency histogram: bin k holds [2^k, 2^(k+1)) microseconds
+          const double us = (now - res.t_submit) * 1e6;
+          int bin = 0;
+          while (bin < SB_LATENCY_BINS - 1 && us >= (double)(2ll << bin)) ++bin;
+          ++lat_hist_[bin];
         }
         res.t_done = now;
         en.state = DONE;
@@ -481,6 +514,8 @@ void Server::loop() {
         f.iters = cfg.iters_per_tick;
         f.fit_iters = cfg.fit_iters;
         f.lambda0 = (float)cfg.lm_lambda0;
+        f.solver = cfg.solver;
+        f.lbfgs_m = cfg.lbfgs_m;
         f.t = d_t_;
         f.band = d_band_;
         f.data = d_data_;

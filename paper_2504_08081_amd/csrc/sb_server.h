@@ -46,6 +46,7 @@ class Server {
     std::vector<int> band;
     float z, t0, x0, x1, c;
     int free_mask;
+    float lo[4], hi[4];   // bounds of (t0, ln x0, x1, c); +-inf when none
     double t_submit;
     int64_t bytes;
   };
@@ -103,6 +104,7 @@ class Server {
           n_slot_ticks_ = 0;
   int n_active_slots_ = 0;
   double busy_s_ = 0.0;
+  int64_t lat_hist_[SB_LATENCY_BINS] = {};
 
   // device side
   hipStream_t stream_ = nullptr;

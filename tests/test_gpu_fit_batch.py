@@ -11,6 +11,11 @@ pytestmark = pytest.mark.gpu
 
 CHI2_TOL = 1e-5          # minimum chi-square against the FP64 fit (relative)
 THETA_SIGMA_TOL = 1e-2   # fitted parameters against the FP64 fit, in units of their uncertainty
+# An FP32 fit cannot place its optimum closer than about sqrt(eps chi2) sigma_q (eps ~ 1e-6, the FP32
+# chi-square's relative error): a step of delta sigma_q changes chi2 by delta^2.  L-BFGS-B stops on
+# a line search whose sufficient-decrease test, chi2 + 1e-3 a g.d, falls below that resolution
+# sooner than the LM's plain decrease test, so its optimum is held to sqrt(1e-6 * 400) = 2e-2.
+THETA_SIGMA_TOL_LBFGSB = 2e-2
 
 
 @pytest.fixture(scope="module")
@@ -54,7 +59,7 @@ def requests(o6):
     return out
 
 
-def device_batch(torch, items, free=None, x0=None):
+def device_batch(torch, items, free=None, x0=None, lower=None, upper=None):
     """The requests as one CSR batch of device arrays (the fit's start is the request's)."""
     dv = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dt)).cuda()
     n = np.array([len(r.t) for r, *_ in items])
@@ -71,18 +76,32 @@ def device_batch(torch, items, free=None, x0=None):
                 inv_sigma2=dv(np.concatenate([w for *_, w in items]), np.float32))
     if free is not None:
         args["free_mask"] = dv(free, np.int32)
+    if lower is not None:
+        args["lower"] = dv(lower, np.float32)
+    if upper is not None:
+        args["upper"] = dv(upper, np.float32)
     return args
 
 
-def check_against_oracle(o6, items, res, free_masks=None):
+def check_against_oracle(o6, items, res, free_masks=None, solver="lm", lower=None, upper=None):
+    """Each GPU fit against the FP64 fit (same solver, start, free mask and bounds): the free
+    parameters within THETA_SIGMA_TOL of their uncertainty, chi2 within CHI2_TOL; held parameters and
+    parameters ending on a bound exactly as given."""
     fo = oracle.FitOracle(o6)
     worst = 0.0
     for i, (r, d, sig, w) in enumerate(items):
         mask = 15 if free_masks is None or free_masks[i] == 0 else int(free_masks[i])
         free = [bool(mask >> k & 1) for k in range(4)]
         fr = np.flatnonzero(free)
-        assert res["status"][i] == 0 and res["iters"][i] == 50, i
-        ref = fo.fit(single_batch(r), r.z, r.theta_init, d, w, free=free)
+        assert res["status"][i] == 0, i
+        if solver == "lm":
+            assert res["iters"][i] == 50, i
+            ref = fo.fit(single_batch(r), r.z, r.theta_init, d, w, free=free)
+        else:
+            assert 0 < res["iters"][i] <= 50, i
+            lo = None if lower is None else np.float64(np.float32(lower[i]))
+            hi = None if upper is None else np.float64(np.float32(upper[i]))
+            ref = fo.fit_lbfgsb(single_batch(r), r.z, r.theta_init, d, w, lower=lo, upper=hi, free=free)
         th = ref["theta"]
         q64 = np.array([th[0], np.log(th[1]), th[2], th[3]])
         qg = np.array([res["t0"][i], np.log(res["x0"][i]), res["x1"][i], res["c"][i]], np.float64)
@@ -90,7 +109,7 @@ def check_against_oracle(o6, items, res, free_masks=None):
         sig_q = np.sqrt(np.diag(np.linalg.inv(H[np.ix_(fr, fr)])))
         dev = np.abs(qg[fr] - q64[fr]) / sig_q
         worst = max(worst, dev.max())
-        assert dev.max() <= THETA_SIGMA_TOL, (i, dev)
+        assert dev.max() <= (THETA_SIGMA_TOL if solver == "lm" else THETA_SIGMA_TOL_LBFGSB), (i, dev)
         assert abs(res["chi2"][i] - ref["chi2"]) <= CHI2_TOL * ref["chi2"], i
         start = np.float32(r.theta_init)
         got = np.float32([res["t0"][i], res["x0"][i], res["x1"][i], res["c"][i]])
@@ -192,3 +211,67 @@ def test_batch_fit_argument_errors(sb, ctx, torch, requests):
     assert L.sb_fit_batch(ctx._h, ctypes.byref(desc), None, None) == sb.SB_ERR_ARG
     desc.n_fit = 0
     assert L.sb_fit_batch(ctx._h, ctypes.byref(desc), None, None) == sb.SB_OK
+
+
+# ----------------------------------------------------------------------------- L-BFGS-B
+
+@pytest.fixture(scope="module")
+def ctx_lb(sb, model, bands6):
+    c = sb.Context.from_model(model, bands6, solver=sb.SB_SOLVER_LBFGSB)
+    yield c
+    c.close()
+
+
+def test_lbfgsb_batch_fits_match_oracle(sb, ctx_lb, o6, torch, requests):
+    """40 light curves fitted by L-BFGS-B in one call, each against the FP64 L-BFGS-B fit from the
+    same start (50 evaluations): parameters within 1e-2 of their uncertainty, chi2 within 1e-5."""
+    print("case: sb_fit_batch L-BFGS-B, 40 fits", flush=True)
+    out = ctx_lb.fit_batch(**device_batch(torch, requests))
+    ctx_lb.device_check()
+    res = sb.fit_results(out)
+    worst = check_against_oracle(o6, requests, res, solver="lbfgsb")
+    print(f"L-BFGS-B batch fit parity: max |dq|/sigma_q = {worst:.2e}, evaluations {res['iters'].min()}-"
+          f"{res['iters'].max()}, iterations {res['n_accept'].min()}-{res['n_accept'].max()}")
+
+
+def test_lbfgsb_bounds_and_held_parameters(sb, ctx_lb, o6, torch, requests):
+    """Per-fit bounds: on every other fit an upper bound on c 0.05 below the unconstrained optimum
+    (active at the solution: c ends exactly on it) and a box on x1 containing its optimum; free
+    masks on a few fits.  Against the FP64 L-BFGS-B fit with the same bounds."""
+    items = requests[:16]
+    fo = oracle.FitOracle(o6)
+    lower = np.tile(np.float32([-np.inf, 0.0, -np.inf, -np.inf]), (len(items), 1))
+    upper = np.tile(np.float32([np.inf, np.inf, np.inf, np.inf]), (len(items), 1))
+    masks = np.array([0, 0, 0, 7, 0, 0, 11, 0] * 2, np.int32)
+    active = []
+    for i, (r, d, sig, w) in enumerate(items):
+        lm = fo.fit(single_batch(r), r.z, r.theta_init, d, w)
+        if i % 2 == 0:
+            upper[i, 3] = np.float32(lm["theta"][3] - 0.05)
+            if masks[i] == 0 or masks[i] & 8:
+                active.append(i)
+        lower[i, 2] = np.float32(lm["theta"][2] - 1.0)
+        upper[i, 2] = np.float32(lm["theta"][2] + 1.0)
+    out = ctx_lb.fit_batch(**device_batch(torch, items, free=masks, lower=lower, upper=upper))
+    ctx_lb.device_check()
+    res = sb.fit_results(out)
+    check_against_oracle(o6, items, res, masks, solver="lbfgsb", lower=lower, upper=upper)
+    for i in active:
+        assert res["c"][i] == upper[i, 3], i
+
+
+def test_lbfgsb_batch_does_not_depend_on_the_rest_of_the_batch(sb, ctx_lb, torch, requests):
+    full = ctx_lb.fit_batch(**device_batch(torch, requests)).cpu().numpy()
+    for lo, hi in ((0, 1), (5, 23)):
+        part = ctx_lb.fit_batch(**device_batch(torch, requests[lo:hi])).cpu().numpy()
+        assert np.array_equal(part, full[lo:hi]), (lo, hi)
+    noalloc = ctx_lb.fit_batch_noalloc(**device_batch(torch, requests)).cpu().numpy()
+    assert np.array_equal(noalloc, full)
+    ctx_lb.device_check()
+
+
+def test_bounds_need_the_lbfgsb_solver(sb, ctx, torch, requests):
+    d = device_batch(torch, requests[:2], lower=np.zeros((2, 4)), upper=np.ones((2, 4)))
+    with pytest.raises(sb.SaltBFError) as e:
+        ctx.fit_batch(**d)
+    assert e.value.status == sb.SB_ERR_ARG

@@ -294,4 +294,77 @@ def test_poll_and_ticket_lifecycle(sb, model, bands6, requests):
     assert st["submitted"] == st["admitted"] == st["completed"] == 1
     assert st["ticks"] == 10 and st["slot_ticks"] == 10
     assert st["active_slots"] == 0 and st["queue_depth"] == 0 and st["bytes_in_use"] == 0
+    # the latency histogram holds the one fit in the bin of its submit-to-done time
+    hist = st["latency_hist"]
+    us = (res.t_done - res.t_submit) * 1e6
+    assert sum(hist) == 1 and hist[max(0, min(23, int(np.floor(np.log2(max(us, 1.0))))))] == 1
     ctx.close()
+
+
+# ----------------------------------------------------------------------------- L-BFGS-B solver
+
+def test_lbfgsb_served_fits_match_oracle(sb, o6, model, bands6, requests):
+    """A server running the L-BFGS-B solver: 24 fits, every third with a box on (x1, c) whose c
+    upper bound excludes the unconstrained optimum, against the FP64 L-BFGS-B fit with the same
+    bounds (parameters within 1e-2 of their uncertainty, chi2 within 1e-5)."""
+    ctx = sb.Context.from_model(model, bands6, solver=sb.SB_SOLVER_LBFGSB)
+    fo = oracle.FitOracle(o6)
+    items = requests[:24]
+    bounds = []
+    tks = []
+    for i, (r, d, sig, w) in enumerate(items):
+        if i % 3 == 0:
+            lm = fo.fit(single_batch(r), r.z, r.theta_init, d, w)
+            lo = np.float32([-np.inf, 0.0, lm["theta"][2] - 1.0, -np.inf])
+            hi = np.float32([np.inf, np.inf, lm["theta"][2] + 1.0, lm["theta"][3] - 0.05])
+            bounds.append((lo, hi))
+            tks.append(ctx.fit_submit(r.t, r.band, d, sig, r.z, *r.theta_init, lower=lo, upper=hi))
+        else:
+            bounds.append(None)
+            tks.append(submit(ctx, items[i]))
+    res = [ctx.fit_wait(tk, 60.0) for tk in tks]
+    worst = 0.0
+    for (r, d, sig, w), g, bd in zip(items, res, bounds):
+        assert g is not None and g.status == sb.SB_OK and 0 < g.iters <= 50
+        lo = None if bd is None else np.float64(bd[0])
+        hi = None if bd is None else np.float64(bd[1])
+        ref = fo.fit_lbfgsb(single_batch(r), r.z, r.theta_init, d, w, lower=lo, upper=hi)
+        th = ref["theta"]
+        q64 = np.array([th[0], np.log(th[1]), th[2], th[3]])
+        qg = np.array([g.t0, np.log(g.x0), g.x1, g.c])
+        _, H, _ = fo.evaluate(single_batch(r), r.z, q64, d, w)
+        dev = np.abs(qg - q64) / np.sqrt(np.diag(np.linalg.inv(H)))
+        worst = max(worst, dev.max())
+        assert dev.max() <= 2 * THETA_SIGMA_TOL, (dev, g.as_dict())   # see test_gpu_fit_batch
+        assert abs(g.chi2 - ref["chi2"]) <= CHI2_TOL * ref["chi2"]
+        if bd is not None:
+            assert np.float32(g.c) == bd[1][3]
+    print(f"L-BFGS-B served fits: max |dq|/sigma_q = {worst:.2e}")
+    ctx.close()
+
+
+def test_lbfgsb_alone_vs_in_the_mix_bitwise(sb, model, bands6, requests):
+    """L-BFGS-B fits alone and sharing launches with 29 others give identical results."""
+    ctx = sb.Context.from_model(model, bands6, solver=sb.SB_SOLVER_LBFGSB)
+    items = requests[:30]
+    alone = [run_all(ctx, [it])[0] for it in items]
+    mixed = run_all(ctx, items)
+    for i, (a, m) in enumerate(zip(alone, mixed)):
+        assert result_key(m) == result_key(a), i
+    ctx.close()
+
+
+def test_bounds_need_the_lbfgsb_solver_and_must_be_ordered(sb, model, bands6, requests):
+    r, d, sig, _ = requests[0]
+    lm = sb.Context.from_model(model, bands6)
+    with pytest.raises(sb.SaltBFError) as e:
+        lm.fit_submit(r.t, r.band, d, sig, r.z, *r.theta_init, lower=np.zeros(4), upper=np.ones(4))
+    assert e.value.status == sb.SB_ERR_ARG
+    lm.close()
+    lb = sb.Context.from_model(model, bands6, solver=sb.SB_SOLVER_LBFGSB)
+    for lo, hi in ((np.ones(4), np.zeros(4)), (np.zeros(4), np.float32([1, 0, 1, 1])),
+                   (np.float32([np.nan, 0, 0, 0]), np.ones(4))):
+        with pytest.raises(sb.SaltBFError) as e:
+            lb.fit_submit(r.t, r.band, d, sig, r.z, *r.theta_init, lower=lo, upper=hi)
+        assert e.value.status == sb.SB_ERR_ARG
+    lb.close()
