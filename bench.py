@@ -39,14 +39,14 @@ PEAK_HBM_GBS = 8000.0
 #     exp 1, weight factors 1 (VJP 5), fraction 1 ........................ FWD 15, VJP 25
 #   per (point, tap) pair gathered into the weight vectors: tap weight 5, one FMA per
 #     weight vector (VJP: 4, plus the difference weight 4) ................ FWD 7, VJP 17
-#   per (surface row, window column) of the row projections: FWD 2 FMA = 4; VJP (on the
-#     surface with precomputed first differences) 2 FMA for the combined node and
-#     difference, 5 FMA = 14
+#   per (surface row, window column) of the row projections: FWD 2 FMA = 4; VJP: the
+#     combined node (1 FMA), the wavelength and phase first differences (1 each) and 6 FMA
+#     into the five projections = 16
 #   per observation: phase coordinate 4, weights 10, taps 8 (VJP 40), partials and
 #     cotangent (VJP 30) .................................................. FWD 24, VJP 90
 W_PT = {"fwd": 15, "vjp": 25}
 W_TAP = {"fwd": 7, "vjp": 17}
-W_CELL = {"fwd": 4, "vjp": 14}
+W_CELL = {"fwd": 4, "vjp": 16}
 W_OBS = {"fwd": 24, "vjp": 90}
 
 
@@ -351,7 +351,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--sweep-samples", type=int, default=1 << 20)
-    ap.add_argument("--legs", default="one,fwd,sweep,big,serve")
+    ap.add_argument("--legs", default="one,fwd,sweep,big,serve,fitbatch,nested")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this size (for calibrating HBM byte counters)")
     args = ap.parse_args()
@@ -540,6 +540,17 @@ def main():
     if "serve" in legs and args.serve_seconds > 0:
         result["serving"] = serve_leg(torch, saltbf, model, bands, args.serve_seconds)
         log(f"serving: {result['serving']}")
+        result["serving_lbfgsb"] = serve_leg(torch, saltbf, model, bands, args.serve_seconds,
+                                             solver=saltbf.SB_SOLVER_LBFGSB)
+        log(f"serving_lbfgsb: {result['serving_lbfgsb']}")
+
+    if "nested" in legs:
+        result["nested"] = nested_leg(torch, saltbf, model, bands)
+        log(f"nested: {result['nested']}")
+
+    if "fitbatch" in legs:
+        result["fit_batch"] = fit_batch_leg(torch, saltbf, model, bands)
+        log(f"fit_batch: {result['fit_batch']}")
 
     if cpu is not None:
         result["cpu_baseline"] = cpu
@@ -574,6 +585,64 @@ def one_sn_leg(torch, saltbf, model, dv, calls=200):
                      "kernel_us": float(durs.mean() * 1e3)}
     ctx.device_check()
     ctx.close()
+    return res
+
+
+def nested_leg(torch, saltbf, model, bands, n_live=500, batch=4096):
+    """One nested-sampling run (sb_nested_sampling) on the sweep's 120-observation light curve:
+    four free parameters with uniform / log-uniform priors around the truth, z fixed; wall time,
+    iterations, likelihood evaluations and ln Z."""
+    sw = synth.sweep_120_obs(n_samples=16)
+    no = len(sw.obs_t)
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    ctx = saltbf.Context.from_model(model, bands)
+    z, t0, x0, x1, c = [float(v) for v in sw.theta_true]
+    f = ctx.bandflux(z=dv(np.float32([z])), t0=dv(np.float32([t0])), x0=dv(np.float32([x0])),
+                     x1=dv(np.float32([x1])), c=dv(np.float32([c])), t=dv(sw.obs_t), band=dv(sw.obs_band),
+                     sn_offsets=dv(np.int32([0, no]))).cpu().numpy()
+    data, sig, w = synth.make_data(f, [0, no], synth.noise_draws(no, k=55))
+    log_norm = float(-np.sum(np.log(np.sqrt(2 * np.pi) * np.float64(sig))))
+    pri = [(0, z, 0), (1, t0 - 1.0, t0 + 1.0), (2, x0 * 0.9, x0 * 1.1), (1, x1 - 0.5, x1 + 0.5), (1, c - 0.05, c + 0.05)]
+    args = (pri, dv(sw.obs_t), dv(sw.obs_band), dv(np.float32(data)), dv(np.float32(w)))
+    ctx.nested_sampling(*args, n_live=50, batch=batch, max_iter=100, log_norm=log_norm)   # warm-up
+    t_start = time.perf_counter()
+    r = ctx.nested_sampling(*args, n_live=n_live, batch=batch, seed=7, dlogz=0.01, log_norm=log_norm)
+    dt = time.perf_counter() - t_start
+    ctx.device_check()
+    ctx.close()
+    return {"n_live": n_live, "batch": batch, "seconds": dt, "iterations": int(r["n_iter"]),
+            "evaluations": int(r["n_eval"]), "batches": int(r["n_batches"]), "evals_per_s": r["n_eval"] * no / dt,
+            "logz": r["logz"], "logz_err": r["logz_err"]}
+
+
+def fit_batch_leg(torch, saltbf, model, bands, n_fit=4096, reps=5):
+    """Batch fits (sb_fit_batch) of 4,096 serving-workload light curves in one call, each solver:
+    milliseconds per call (10 launches of 5 iterations) and fits per second."""
+    reqs = synth.fit_requests(n_fit, k=4)
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    n_s = np.array([len(r.t) for r in reqs])
+    off = np.zeros(n_fit + 1, np.int32)
+    off[1:] = np.cumsum(n_s)
+    th = np.array([r.theta_true for r in reqs])
+    ti = np.array([r.theta_init for r in reqs])
+    zz = np.float32([r.z for r in reqs])
+    t, band = dv(np.float32(np.concatenate([r.t for r in reqs]))), dv(np.int32(np.concatenate([r.band for r in reqs])))
+    res = {"n_fit": n_fit, "n_obs": int(off[-1])}
+    for name, solver in (("lm", saltbf.SB_SOLVER_LM), ("lbfgsb", saltbf.SB_SOLVER_LBFGSB)):
+        ctx = saltbf.Context.from_model(model, bands, solver=solver)
+        f = ctx.bandflux(z=dv(zz), t0=dv(np.float32(th[:, 0])), x0=dv(np.float32(th[:, 1])),
+                         x1=dv(np.float32(th[:, 2])), c=dv(np.float32(th[:, 3])), t=t, band=band,
+                         sn_offsets=dv(off)).cpu().numpy()
+        data, _, w = synth.make_data(f, off, np.concatenate([r.normals for r in reqs]))
+        args = dict(z=dv(zz), t0=dv(np.float32(ti[:, 0])), x0=dv(np.float32(ti[:, 1])), x1=dv(np.float32(ti[:, 2])),
+                    c=dv(np.float32(ti[:, 3])), t=t, band=band, fit_offsets=dv(off), data=dv(data), inv_sigma2=dv(w))
+        out = torch.empty((n_fit, saltbf.FIT_OUT_WORDS), dtype=torch.int32, device="cuda")
+        durs, _ = time_launches(torch, lambda: ctx.fit_batch(**args, out=out), reps, 1)
+        ctx.device_check()
+        r = saltbf.fit_results(out)
+        res[name] = {"ms_per_call": float(durs.mean()), "fits_per_s": n_fit / (durs.mean() * 1e-3),
+                     "ok": int(np.sum(r["status"] == 0)), "mean_evaluations": float(r["iters"].mean())}
+        ctx.close()
     return res
 
 
@@ -623,7 +692,8 @@ def serve_leg(torch, saltbf, model, bands, seconds, **config):
     done = [x for x in res if x is not None]
     span = max(x.t_done for x in done) - min(x.t_submit for x in done)
     ok = sum(1 for x in done if x.status == 0)
-    return {"requests": n_req, "rate_req_s": rate, "completed_ok": ok, "fits_per_s": len(done) / span,
+    return {"solver": "lbfgsb" if config.get("solver") == saltbf.SB_SOLVER_LBFGSB else "lm",
+            "requests": n_req, "rate_req_s": rate, "completed_ok": ok, "fits_per_s": len(done) / span,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "latency_from": "scheduled arrival",
             "submit_p50_ms": float(np.percentile(lat_sub, 50)), "submit_p99_ms": float(np.percentile(lat_sub, 99)),

@@ -50,6 +50,7 @@ extern "C" {
 #define SB_MAX_BAND_POINTS 2048   /* quadrature nodes per band */
 #define SB_MAX_CL_DEGREE 8
 #define SB_N_PARAMS 5             /* gradient order: z, t0, x0, x1, c */
+#define SB_LATENCY_BINS 24        /* fit latency histogram bins (sb_stats_t) */
 
 typedef int32_t sb_status;
 enum {
@@ -103,7 +104,23 @@ typedef struct {
   int64_t lds_limit_bytes;   /* LDS a workgroup may use; 0 (default): the device's per-workgroup maximum.
                                 Kernels run several waves per workgroup where that fits, else one;
                                 bands whose one-wave form does not fit are refused by sb_add_band. */
+  int32_t solver;            /* fit solver of the server and the batch fits: SB_SOLVER_LM (default) or
+                                SB_SOLVER_LBFGSB */
+  int32_t lbfgs_m;           /* L-BFGS-B correction pairs kept, 1..5 (default 5) */
 } sb_config;
+
+/* Fit solvers.  Both vary (t0, ln x0, x1, c) with z fixed and minimise
+ * chi2 = sum_i (d_i - f_i)^2 / sigma_i^2 with cfg.fit_iters evaluations after the
+ * one at the start.
+ * SB_SOLVER_LM: Levenberg-Marquardt damped Gauss-Newton (see the fit server).
+ * SB_SOLVER_LBFGSB: the bounded limited-memory quasi-Newton method of the
+ *   paper's optimisation example (L-BFGS-B; Byrd, Lu, Nocedal and Zhu 1995):
+ *   BFGS matrix from the last cfg.lbfgs_m correction pairs, generalized Cauchy
+ *   point along the projected gradient path, subspace step cut back to the box,
+ *   strong-Wolfe line search (1e-3, 0.9); bounds per fit (requests: has_bounds,
+ *   lower, upper; batch fits: lower, upper arrays).  A held parameter (free_mask)
+ *   is a variable whose two bounds equal its start. */
+enum { SB_SOLVER_LM = 0, SB_SOLVER_LBFGSB = 1 };
 
 void sb_config_default(sb_config *cfg);
 
@@ -131,6 +148,29 @@ sb_status sb_add_band(sb_ctx *ctx, const double *wave, const double *trans, int3
  * count.  SB_ERR_ARG if it exceeds cap. */
 sb_status sb_band_grid(const double *wave, const double *trans, int32_t n, double max_spacing, int32_t rule,
                        int32_t cap, float *lam_out, float *weight_out, int32_t *n_points);
+
+/* Bandpass files (the paper's bandpass loading from a file): a text file of two
+ * numeric columns per line, wavelength [Angstrom] and transmission, separated by
+ * spaces, tabs or a comma; '#' starts a comment; blank lines are skipped.  Host
+ * only: reads at most cap rows into wave/trans, *n receives the row count.
+ * SB_ERR_ARG if the file cannot be read, a line does not parse, or there are
+ * more than cap rows (*n then holds the count needed). */
+sb_status sb_read_band_file(const char *path, double *wave, double *trans, int32_t cap, int32_t *n);
+
+/* sb_read_band_file followed by sb_add_band (at most 65,536 rows). */
+sb_status sb_add_band_file(sb_ctx *ctx, const char *path, int32_t *band_id);
+
+/* AB magnitude system: m_AB = -2.5 log10(f / F_AB), where F_AB is the bandflux
+ * of the AB reference source, f_nu = 10^(-48.60/2.5) erg s^-1 cm^-2 Hz^-1 at
+ * every frequency, through the band with the same quadrature as the model:
+ * F_AB = sum_k w_k T_k f_nu / (h lam_k) (the lam/(hc) photon weight times
+ * f_lam = f_nu c / lam^2).  Computed in FP64 at registration.
+ * sb_band_zeropoint: the value for a registered band; sb_band_zeropoint_ab: the
+ * same for band samples, host only (no context), with the given spacing and rule. */
+enum { SB_MAGSYS_AB = 0 };
+sb_status sb_band_zeropoint(sb_ctx *ctx, int32_t band_id, int32_t magsys, double *zp_flux);
+sb_status sb_band_zeropoint_ab(const double *wave, const double *trans, int32_t n, double max_spacing,
+                               int32_t rule, double *zp_flux);
 
 /* Batch flags. */
 enum {
@@ -202,6 +242,11 @@ typedef struct {
   uint32_t free_mask;        /* parameters the fit varies: an OR of SB_FREE_*; 0 means SB_FREE_ALL.
                                 The others stay at their starting values (the LM system is solved
                                 over the free parameters only).  Other bits: SB_ERR_ARG. */
+  int32_t has_bounds;        /* nonzero: lower/upper bound (t0, x0, x1, c) (SB_SOLVER_LBFGSB only,
+                                else SB_ERR_ARG); +-inf for none, an x0 lower bound <= 0 is none,
+                                an x0 upper bound must be > 0; lower <= upper.  A start outside
+                                the box starts from its projection onto it. */
+  float lower[4], upper[4];
 } sb_fit_request;
 
 enum { SB_FREE_T0 = 1, SB_FREE_X0 = 2, SB_FREE_X1 = 4, SB_FREE_C = 8, SB_FREE_ALL = 15 };
@@ -251,6 +296,9 @@ typedef struct {
   const int32_t *band;                 /* device [n_obs] */
   const int32_t *fit_offsets;          /* device CSR [n_fit + 1] */
   const float *data, *inv_sigma2;      /* device [n_obs] */
+  const float *lower, *upper;          /* device [n_fit][4] bounds of (t0, x0, x1, c) or NULL (none);
+                                          SB_SOLVER_LBFGSB only (else SB_ERR_ARG); as in sb_fit_request,
+                                          a fit whose bounds are malformed ends SB_FIT_DIVERGED */
 } sb_fit_batch_desc;
 
 /* One fit's result (device array [n_fit] written by the last launch). */
@@ -263,7 +311,7 @@ typedef struct {
 } sb_fit_out;
 
 /* Fits every supernova of the batch (see above).  The per-fit state scratch
- * (cfg-independent, about 128 bytes per fit) is allocated stream-ordered for the
+ * (cfg-independent, about 400 bytes per fit) is allocated stream-ordered for the
  * call and released after its last launch.  Asynchronous; out must stay valid
  * until the stream reaches the end of the call's work.  SB_ERR_ARG for NULL
  * pointers or sizes; n_fit = 0 does nothing. */
@@ -273,12 +321,64 @@ sb_status sb_fit_batch(sb_ctx *ctx, const sb_fit_batch_desc *batch, sb_fit_out *
  * capture, serving loops that must not call hipMalloc): identical results to
  * sb_fit_batch, with the per-fit state in a fixed device array that the library
  * holds on each GPU it runs on until the process ends (SB_FIT_NOALLOC_MAX fits,
- * about 128 bytes each).  It calls no allocation routine.  n_fit above
+ * about 400 bytes each, 3.2 MB).  It calls no allocation routine.  n_fit above
  * SB_FIT_NOALLOC_MAX is SB_ERR_ARG.  Every call on one GPU uses the same array:
  * calls whose work overlaps on a GPU (different streams, or different contexts
  * on the same device) race and must be serialised by the caller. */
 #define SB_FIT_NOALLOC_MAX 8192
 sb_status sb_fit_batch_noalloc(sb_ctx *ctx, const sb_fit_batch_desc *batch, sb_fit_out *out, void *hip_stream);
+
+/* ------------------------------------------------------------ nested sampling
+ * The paper's nested-sampling example (section "Implementation", the example
+ * scripts): Skilling's nested sampling of one light curve's posterior, with
+ * ln L(theta) = log_norm - chi2(theta)/2 over an observation table on the device
+ * (t, band, data, inv_sigma2 [n_obs]) and independent priors on z, t0, x0, x1, c.
+ * N live points; each iteration the lowest ln L becomes a dead point with prior
+ * mass X_i = exp(-i/N) and log weight ln(X_{i-1} - X_i), and is replaced by a
+ * draw from the prior restricted to L > L*; ln Z and the information H
+ * accumulate; the run stops after max_iter dead points, at max_evals likelihood
+ * evaluations, or when ln(Z + L_max X) - ln Z < dlogz; the live points then join
+ * with ln weight ln(X_final / N).  Constrained draws: uniform in the unit cube
+ * inside the live points' box widened by `enlarge` about its centre, mapped by
+ * the prior transform, evaluated `batch` at a time by one broadcast chi-square
+ * launch; candidates above L* are kept in draw order for the following
+ * iterations.  Draw n's unit-cube coordinates are Philox4x64-10 outputs (counter
+ * (n, d div 4, 0, 0), key (seed, 0x5A17BF1A5A17BF1A), output d mod 4, mapped to
+ * ((x >> 11) + 1/2) 2^-53); draws 0..N-1 are the initial live points.  A sample
+ * whose band windows leave the surface has ln L = -inf (and sets the range flag).
+ * Synchronous: the host loop waits on hip_stream for every batch. */
+enum { SB_PRIOR_FIXED = 0, SB_PRIOR_UNIFORM = 1, SB_PRIOR_LOG_UNIFORM = 2 };
+typedef struct {
+  int32_t kind;              /* fixed: value a; uniform on [a, b]; log-uniform on [a, b], 0 < a < b */
+  double a, b;
+} sb_prior;
+typedef struct {
+  sb_prior prior[5];         /* z, t0, x0, x1, c */
+  int32_t n_live;            /* >= 2 */
+  int32_t batch;             /* candidates per device evaluation, >= 1 */
+  int64_t max_iter;          /* dead points at most (the dead_* outputs hold this many rows) */
+  int64_t max_evals;         /* likelihood evaluations at most */
+  double dlogz;              /* stopping tolerance on ln Z (0: run to max_iter or max_evals) */
+  double enlarge;            /* box widening factor, >= 1 */
+  uint64_t seed;             /* first key word of the draws */
+  double log_norm;           /* constant of ln L */
+} sb_ns_config;
+typedef struct {
+  double logz, logz_err, information;   /* ln Z, sqrt(H / N), H */
+  int64_t n_iter, n_eval, n_batches;
+  int32_t stopped_on_evals;
+} sb_ns_summary;
+
+/* Outputs are host arrays owned by the caller, each may be NULL: dead_theta
+ * [max_iter][5], dead_logl, dead_logw, dead_draw [max_iter] (rows 0..n_iter-1
+ * written); live_theta [n_live][5], live_logl, live_logw [n_live]. */
+sb_status sb_nested_sampling(sb_ctx *ctx, const sb_ns_config *cfg, int32_t n_obs, const float *t, const int32_t *band,
+                             const float *data, const float *inv_sigma2, double *dead_theta, double *dead_logl,
+                             double *dead_logw, int64_t *dead_draw, double *live_theta, double *live_logl,
+                             double *live_logw, sb_ns_summary *out, void *hip_stream);
+
+/* Host-only: one Philox4x64-10 block (the draws' generator), for checking it. */
+void sb_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 
 typedef struct {
   int64_t submitted, admitted, completed, cancelled, rejected;
@@ -288,6 +388,9 @@ typedef struct {
   int64_t bytes_in_use, budget_bytes;
   double busy_seconds;         /* host time with at least one fit resident */
   int64_t slot_ticks;          /* fits run, summed over launches (slot_ticks / ticks: mean fits per launch) */
+  int64_t latency_hist[SB_LATENCY_BINS];  /* completed fits by submit-to-done latency: bin k counts
+                                             [2^k, 2^(k+1)) microseconds; bin 0 also everything below,
+                                             the last bin everything above */
 } sb_stats_t;
 
 sb_status sb_stats(sb_ctx *ctx, sb_stats_t *out);

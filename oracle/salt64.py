@@ -36,6 +36,7 @@ import numpy as np
 H_PLANCK = 6.62607015e-27       # erg s
 C_LIGHT_AA = 2.99792458e18      # Angstrom / s
 HC = H_PLANCK * C_LIGHT_AA      # erg Angstrom
+FNU_AB = 10.0 ** (-0.4 * 48.60)  # AB reference source, erg s^-1 cm^-2 Hz^-1 (m_AB = 0)
 
 PARAM_NAMES = ("z", "t0", "x0", "x1", "c")
 
@@ -68,6 +69,15 @@ def band_grid(wave, trans, spacing=5.0, rule="trapezoid"):
         raise ValueError(f"unknown quadrature rule {rule!r}")
     T = np.interp(lam, wave, trans)
     return lam, T, w
+
+
+def ab_zeropoint(wave, trans, spacing=5.0, rule="trapezoid"):
+    """Bandflux of the AB reference source (f_nu = FNU_AB at every frequency) through the band, with
+    the band's own quadrature: the photon weight lam/(hc) times f_lam = f_nu c / lam^2, summed with
+    the trapezoid (or midpoint) weights.  m_AB = -2.5 log10(f / this)."""
+    lam, T, w = band_grid(wave, trans, spacing, rule)
+    f_lam = FNU_AB * C_LIGHT_AA / lam ** 2
+    return float(np.sum(w * T * f_lam * lam / HC))
 
 
 # ----------------------------------------------------------------------------- interpolation

@@ -15,9 +15,13 @@ class Server;
 sb_status set_error(sb_status st, const std::string& msg);
 double now_seconds();
 
-// Quadrature grid of one band (trapezoid or midpoint rule), float64: nodes, and W_k = w_k lam_k T_k / (hc).
+// Quadrature grid of one band (trapezoid or midpoint rule), float64: nodes, and W_k = w_k lam_k T_k / (hc);
+// zp_ab (optional) receives the AB zero-point flux sum_k w_k T_k f_nu,AB / (h lam_k).
 sb_status build_band_grid(const double* wave, const double* trans, int n, double spacing, int rule,
-                          std::vector<double>& lam, std::vector<double>& W);
+                          std::vector<double>& lam, std::vector<double>& W, double* zp_ab = nullptr);
+
+// Rows of a two-column bandpass text file.
+sb_status read_band_file(const char* path, std::vector<double>& wave, std::vector<double>& trans);
 
 }  // namespace sbh
 
@@ -34,6 +38,7 @@ struct sb_ctx {
   int max_pts = 0;
   int jcap = 0;
   std::vector<double> band_lo, band_hi; // sample range of each band
+  std::vector<double> band_zp_ab;       // AB zero-point flux of each band
   int n_cu = 1;
   size_t max_lds = 65536;
   std::mutex mu;                       // band registration, server start

@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <climits>
+#include <cstdio>
 #include <cstring>
 #include <new>
 
@@ -13,7 +15,10 @@ namespace {
 thread_local std::string g_last_error;
 
 // h c with the exact SI values of h (erg s) and c (Angstrom / s): erg Angstrom.
-constexpr double HC_ERG_ANGSTROM = 6.62607015e-27 * 2.99792458e18;
+constexpr double H_ERG_S = 6.62607015e-27;
+constexpr double HC_ERG_ANGSTROM = H_ERG_S * 2.99792458e18;
+// AB reference spectral flux density: m_AB = -2.5 log10(f_nu / (erg s^-1 cm^-2 Hz^-1)) - 48.60 = 0.
+const double FNU_AB = std::pow(10.0, -0.4 * 48.60);
 
 bool finite_all(const double* a, int n) {
   for (int i = 0; i < n; ++i)
@@ -39,7 +44,7 @@ double now_seconds() {
 }
 
 sb_status build_band_grid(const double* wave, const double* trans, int n, double spacing, int rule,
-                          std::vector<double>& lam, std::vector<double>& W) {
+                          std::vector<double>& lam, std::vector<double>& W, double* zp_ab) {
   if (!wave || !trans || n < 2) return set_error(SB_ERR_ARG, "band: need at least 2 samples");
   if (!(spacing > 0.0) || !std::isfinite(spacing)) return set_error(SB_ERR_ARG, "band: spacing must be > 0");
   if (rule != SB_QUAD_TRAPEZOID && rule != SB_QUAD_MIDPOINT) return set_error(SB_ERR_ARG, "band: unknown rule");
@@ -63,6 +68,7 @@ sb_status build_band_grid(const double* wave, const double* trans, int n, double
   lam.assign(n_nodes, 0.0);
   W.assign(n_nodes, 0.0);
   int seg = 0;
+  double zp = 0.0;
   for (long k = 0; k < n_nodes; ++k) {
     const double x = mid ? L + delta * ((double)k + 0.5) : ((k == N) ? U : L + delta * (double)k);
     while (seg < n - 2 && x > wave[seg + 1]) ++seg;
@@ -72,8 +78,51 @@ sb_status build_band_grid(const double* wave, const double* trans, int n, double
     const double w = (!mid && (k == 0 || k == N)) ? 0.5 * delta : delta;
     lam[k] = x;
     W[k] = w * x * T / HC_ERG_ANGSTROM;
+    zp += w * T / x;
   }
+  if (zp_ab) *zp_ab = zp * FNU_AB / H_ERG_S;
   return SB_OK;
+}
+
+// Two numeric columns per line ('#' comments, blank lines skipped; spaces, tabs or a comma).
+sb_status read_band_file(const char* path, std::vector<double>& wave, std::vector<double>& trans) {
+  wave.clear();
+  trans.clear();
+  if (!path) return set_error(SB_ERR_ARG, "band file: NULL path");
+  FILE* fh = std::fopen(path, "r");
+  if (!fh) return set_error(SB_ERR_ARG, std::string("band file: cannot open ") + path);
+  char line[4096];
+  int lineno = 0;
+  sb_status st = SB_OK;
+  while (std::fgets(line, sizeof line, fh)) {
+    ++lineno;
+    if (!std::strchr(line, '\n') && !std::feof(fh)) {
+      st = set_error(SB_ERR_ARG, "band file: line " + std::to_string(lineno) + " too long");
+      break;
+    }
+    if (char* hash = std::strchr(line, '#')) *hash = '\0';
+    for (char* c = line; *c; ++c)
+      if (*c == ',') *c = ' ';
+    char* p = line;
+    while (*p == ' ' || *p == '\t' || *p == '\r' || *p == '\n') ++p;
+    if (!*p) continue;
+    char* end = nullptr;
+    const double a = std::strtod(p, &end);
+    const bool ok_a = end != p;
+    p = end;
+    const double b = std::strtod(p, &end);
+    const bool ok_b = end != p;
+    p = end;
+    while (*p == ' ' || *p == '\t' || *p == '\r' || *p == '\n') ++p;
+    if (!ok_a || !ok_b || *p) {
+      st = set_error(SB_ERR_ARG, "band file: line " + std::to_string(lineno) + " is not two numbers");
+      break;
+    }
+    wave.push_back(a);
+    trans.push_back(b);
+  }
+  std::fclose(fh);
+  return st;
 }
 
 }  // namespace sbh
@@ -112,6 +161,8 @@ void sb_config_default(sb_config* cfg) {
   cfg->lm_lambda0 = 1e-3;
   cfg->quad_rule = SB_QUAD_TRAPEZOID;
   cfg->lds_limit_bytes = 0;
+  cfg->solver = SB_SOLVER_LM;
+  cfg->lbfgs_m = 5;
 }
 
 sb_status sb_band_grid(const double* wave, const double* trans, int32_t n, double max_spacing, int32_t rule,
@@ -165,7 +216,9 @@ sb_status sb_create(const sb_model_desc* md, const sb_config* cfg_in, int device
   if (!(cfg.max_spacing > 0) || cfg.max_obs_per_fit < 1 || cfg.max_obs_per_fit > 1024 || cfg.max_slots < 1 ||
       cfg.max_slots > 65536 || cfg.hbm_budget_bytes < 0 || cfg.iters_per_tick < 1 || cfg.fit_iters < 0 ||
       !(cfg.lm_lambda0 > 0) || cfg.lds_limit_bytes < 0 ||
-      (cfg.quad_rule != SB_QUAD_TRAPEZOID && cfg.quad_rule != SB_QUAD_MIDPOINT))
+      (cfg.quad_rule != SB_QUAD_TRAPEZOID && cfg.quad_rule != SB_QUAD_MIDPOINT) ||
+      (cfg.solver != SB_SOLVER_LM && cfg.solver != SB_SOLVER_LBFGSB) || cfg.lbfgs_m < 1 ||
+      cfg.lbfgs_m > sbk::LB_MAX_M)
     return set_error(SB_ERR_ARG, "sb_create: bad configuration");
 
   hipError_t e = hipSetDevice(device);
@@ -256,7 +309,8 @@ sb_status sb_add_band(sb_ctx* ctx, const double* wave, const double* trans, int3
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (ctx->n_bands >= SB_MAX_BANDS) return set_error(SB_ERR_ARG, "sb_add_band: registry full");
   std::vector<double> lam, W;
-  sb_status st = sbh::build_band_grid(wave, trans, n, ctx->cfg.max_spacing, ctx->cfg.quad_rule, lam, W);
+  double zp_ab = 0.0;
+  sb_status st = sbh::build_band_grid(wave, trans, n, ctx->cfg.max_spacing, ctx->cfg.quad_rule, lam, W, &zp_ab);
   if (st != SB_OK) return st;
   const int np = (int)lam.size();
   // surface window of the band for rest wavelengths lam/(1+z), z >= WINDOW_Z_MIN: at most
@@ -280,12 +334,53 @@ sb_status sb_add_band(sb_ctx* ctx, const double* wave, const double* trans, int3
   if (e != hipSuccess) return hip_fail(e, "sb_add_band: upload");
   ctx->band_lo.push_back(wave[0]);
   ctx->band_hi.push_back(wave[n - 1]);
+  ctx->band_zp_ab.push_back(zp_ab);
   ctx->max_pts = std::max(ctx->max_pts, np);
   ctx->jcap = jcap;
   ctx->n_bands = id + 1;
   ctx->km.n_bands = ctx->n_bands;
   *band_id = id;
   return SB_OK;
+}
+
+sb_status sb_read_band_file(const char* path, double* wave, double* trans, int32_t cap, int32_t* n) {
+  if (!n) return set_error(SB_ERR_ARG, "sb_read_band_file: n is NULL");
+  std::vector<double> w, t;
+  sb_status st = sbh::read_band_file(path, w, t);
+  if (st != SB_OK) return st;
+  *n = (int32_t)std::min<size_t>(w.size(), (size_t)INT32_MAX);
+  if ((int64_t)w.size() > cap) return set_error(SB_ERR_ARG, "sb_read_band_file: more rows than cap");
+  if (!w.empty() && (!wave || !trans)) return set_error(SB_ERR_ARG, "sb_read_band_file: NULL output");
+  for (size_t i = 0; i < w.size(); ++i) {
+    wave[i] = w[i];
+    trans[i] = t[i];
+  }
+  return SB_OK;
+}
+
+sb_status sb_add_band_file(sb_ctx* ctx, const char* path, int32_t* band_id) {
+  if (!ctx || !band_id) return set_error(SB_ERR_ARG, "sb_add_band_file: NULL argument");
+  std::vector<double> w, t;
+  sb_status st = sbh::read_band_file(path, w, t);
+  if (st != SB_OK) return st;
+  if (w.size() > 65536) return set_error(SB_ERR_ARG, "sb_add_band_file: more than 65,536 rows");
+  return sb_add_band(ctx, w.data(), t.data(), (int32_t)w.size(), band_id);
+}
+
+sb_status sb_band_zeropoint(sb_ctx* ctx, int32_t band_id, int32_t magsys, double* zp_flux) {
+  if (!ctx || !zp_flux) return set_error(SB_ERR_ARG, "sb_band_zeropoint: NULL argument");
+  if (magsys != SB_MAGSYS_AB) return set_error(SB_ERR_ARG, "sb_band_zeropoint: unknown magnitude system");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (band_id < 0 || band_id >= ctx->n_bands) return set_error(SB_ERR_ARG, "sb_band_zeropoint: unknown band");
+  *zp_flux = ctx->band_zp_ab[band_id];
+  return SB_OK;
+}
+
+sb_status sb_band_zeropoint_ab(const double* wave, const double* trans, int32_t n, double max_spacing, int32_t rule,
+                               double* zp_flux) {
+  if (!zp_flux) return set_error(SB_ERR_ARG, "sb_band_zeropoint_ab: NULL output");
+  std::vector<double> lam, W;
+  return sbh::build_band_grid(wave, trans, n, max_spacing, rule, lam, W, zp_flux);
 }
 
 static sb_status check_batch(const sb_ctx* ctx, const sb_batch* b, const char* who) {
@@ -370,6 +465,8 @@ static sb_status check_fit_batch(const sb_ctx* ctx, const sb_fit_batch_desc* b, 
     return set_error(SB_ERR_ARG, w + ": NULL parameter, offset or output array");
   if (b->n_obs > 0 && (!b->t || !b->band || !b->data || !b->inv_sigma2))
     return set_error(SB_ERR_ARG, w + ": NULL observation array");
+  if ((b->lower || b->upper) && ctx->cfg.solver != SB_SOLVER_LBFGSB)
+    return set_error(SB_ERR_ARG, w + ": bounds need the L-BFGS-B solver (sb_config.solver)");
   return SB_OK;
 }
 
@@ -378,8 +475,12 @@ static sbk::KFit make_kfit_batch(sb_ctx* ctx, const sb_fit_batch_desc* b, sb_fit
   sbk::KFit f{};
   f.slots = slots;
   f.lambda0 = (float)ctx->cfg.lm_lambda0;
+  f.solver = ctx->cfg.solver;
+  f.lbfgs_m = ctx->cfg.lbfgs_m;
   f.err = ctx->d_err;
   f.b_off = b->fit_offsets;
+  f.b_lower = b->lower;
+  f.b_upper = b->upper;
   f.b_z = b->z; f.b_t0 = b->t0; f.b_x0 = b->x0; f.b_x1 = b->x1; f.b_c = b->c;
   f.b_free = b->free_mask;
   f.b_t = b->t; f.b_band = b->band; f.b_data = b->data; f.b_w = b->inv_sigma2;

@@ -22,6 +22,9 @@ SB_ERR_BUDGET, SB_ERR_STATE, SB_ERR_NOTFOUND = -5, -6, -7
 SB_OBS_BROADCAST, SB_OUT_CHI2 = 1, 2
 SB_QUAD_TRAPEZOID, SB_QUAD_MIDPOINT = 0, 1
 SB_FREE_T0, SB_FREE_X0, SB_FREE_X1, SB_FREE_C, SB_FREE_ALL = 1, 2, 4, 8, 15
+SB_SOLVER_LM, SB_SOLVER_LBFGSB = 0, 1
+SB_MAGSYS_AB = 0
+SB_PRIOR_FIXED, SB_PRIOR_UNIFORM, SB_PRIOR_LOG_UNIFORM = 0, 1, 2
 SB_MAX_BANDS, SB_MAX_BAND_POINTS, SB_N_PARAMS = 64, 2048, 5
 SB_FIT_NOALLOC_MAX = 8192
 
@@ -29,6 +32,8 @@ EXPORTED = (
     "sb_config_default", "sb_create", "sb_destroy", "sb_add_band", "sb_band_grid", "sb_bandflux",
     "sb_bandflux_vjp", "sb_device_check", "sb_fit_submit", "sb_fit_poll", "sb_fit_wait", "sb_fit_cancel",
     "sb_stats", "sb_status_string", "sb_last_error", "sb_fit_batch", "sb_fit_batch_noalloc",
+    "sb_read_band_file", "sb_add_band_file", "sb_band_zeropoint", "sb_band_zeropoint_ab",
+    "sb_nested_sampling", "sb_philox4x64_10",
 )
 
 _f32p = ctypes.POINTER(ctypes.c_float)
@@ -50,7 +55,7 @@ class Config(ctypes.Structure):
                 ("max_slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64),
                 ("iters_per_tick", ctypes.c_int32), ("fit_iters", ctypes.c_int32),
                 ("lm_lambda0", ctypes.c_double), ("quad_rule", ctypes.c_int32),
-                ("lds_limit_bytes", ctypes.c_int64)]
+                ("lds_limit_bytes", ctypes.c_int64), ("solver", ctypes.c_int32), ("lbfgs_m", ctypes.c_int32)]
 
 
 class Batch(ctypes.Structure):
@@ -65,7 +70,8 @@ class FitRequest(ctypes.Structure):
     _fields_ = [("n_obs", ctypes.c_int32), ("t", ctypes.c_void_p), ("band", ctypes.c_void_p),
                 ("data", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
                 ("z", ctypes.c_float), ("t0", ctypes.c_float), ("x0", ctypes.c_float),
-                ("x1", ctypes.c_float), ("c", ctypes.c_float), ("free_mask", ctypes.c_uint32)]
+                ("x1", ctypes.c_float), ("c", ctypes.c_float), ("free_mask", ctypes.c_uint32),
+                ("has_bounds", ctypes.c_int32), ("lower", ctypes.c_float * 4), ("upper", ctypes.c_float * 4)]
 
 
 class FitResult(ctypes.Structure):
@@ -83,7 +89,8 @@ class FitBatchDesc(ctypes.Structure):
                 ("z", ctypes.c_void_p), ("t0", ctypes.c_void_p), ("x0", ctypes.c_void_p),
                 ("x1", ctypes.c_void_p), ("c", ctypes.c_void_p), ("free_mask", ctypes.c_void_p),
                 ("t", ctypes.c_void_p), ("band", ctypes.c_void_p), ("fit_offsets", ctypes.c_void_p),
-                ("data", ctypes.c_void_p), ("inv_sigma2", ctypes.c_void_p)]
+                ("data", ctypes.c_void_p), ("inv_sigma2", ctypes.c_void_p),
+                ("lower", ctypes.c_void_p), ("upper", ctypes.c_void_p)]
 
 
 class FitOut(ctypes.Structure):
@@ -96,15 +103,34 @@ class FitOut(ctypes.Structure):
 FIT_OUT_WORDS = 8
 
 
+class Prior(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("a", ctypes.c_double), ("b", ctypes.c_double)]
+
+
+class NsConfig(ctypes.Structure):
+    _fields_ = [("prior", Prior * 5), ("n_live", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("max_iter", ctypes.c_int64), ("max_evals", ctypes.c_int64), ("dlogz", ctypes.c_double),
+                ("enlarge", ctypes.c_double), ("seed", ctypes.c_uint64), ("log_norm", ctypes.c_double)]
+
+
+class NsSummary(ctypes.Structure):
+    _fields_ = [("logz", ctypes.c_double), ("logz_err", ctypes.c_double), ("information", ctypes.c_double),
+                ("n_iter", ctypes.c_int64), ("n_eval", ctypes.c_int64), ("n_batches", ctypes.c_int64),
+                ("stopped_on_evals", ctypes.c_int32)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("cancelled", ctypes.c_int64), ("rejected", ctypes.c_int64), ("ticks", ctypes.c_int64),
                 ("queue_depth", ctypes.c_int32), ("active_slots", ctypes.c_int32),
                 ("bytes_in_use", ctypes.c_int64), ("budget_bytes", ctypes.c_int64),
-                ("busy_seconds", ctypes.c_double), ("slot_ticks", ctypes.c_int64)]
+                ("busy_seconds", ctypes.c_double), ("slot_ticks", ctypes.c_int64),
+                ("latency_hist", ctypes.c_int64 * 24)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["latency_hist"] = list(self.latency_hist)
+        return d
 
 
 class SaltBFError(RuntimeError):
@@ -156,6 +182,21 @@ def lib():
         L.sb_fit_batch.restype = st
         L.sb_fit_batch_noalloc.argtypes = [vp, ctypes.POINTER(FitBatchDesc), vp, vp]
         L.sb_fit_batch_noalloc.restype = st
+        L.sb_read_band_file.argtypes = [ctypes.c_char_p, _f64p, _f64p, ctypes.c_int32, _i32p]
+        L.sb_read_band_file.restype = st
+        L.sb_add_band_file.argtypes = [vp, ctypes.c_char_p, _i32p]
+        L.sb_add_band_file.restype = st
+        L.sb_band_zeropoint.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _f64p]
+        L.sb_band_zeropoint.restype = st
+        L.sb_band_zeropoint_ab.argtypes = [_f64p, _f64p, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _f64p]
+        L.sb_band_zeropoint_ab.restype = st
+        L.sb_nested_sampling.argtypes = [vp, ctypes.POINTER(NsConfig), ctypes.c_int32, vp, vp, vp, vp, _f64p, _f64p,
+                                         _f64p, ctypes.POINTER(ctypes.c_int64), _f64p, _f64p, _f64p,
+                                         ctypes.POINTER(NsSummary), vp]
+        L.sb_nested_sampling.restype = st
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        L.sb_philox4x64_10.argtypes = [u64p, u64p, u64p]
+        L.sb_philox4x64_10.restype = None
         L.sb_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.sb_stats.restype = st
         L.sb_status_string.argtypes = [st]
@@ -193,6 +234,39 @@ def band_grid(wave, trans, max_spacing=5.0, rule=0):
                               int(rule), SB_MAX_BAND_POINTS, lam.ctypes.data_as(_f32p), W.ctypes.data_as(_f32p),
                               ctypes.byref(n)), "sb_band_grid")
     return lam[: n.value].copy(), W[: n.value].copy()
+
+
+def read_band_file(path):
+    """Rows (wave, trans) of a two-column bandpass text file, as the library reads it (host only)."""
+    p = os.fsencode(path)
+    n = ctypes.c_int32(0)
+    st = lib().sb_read_band_file(p, None, None, 0, ctypes.byref(n))
+    if st < 0 and n.value == 0:
+        _check(st, "sb_read_band_file")
+    w = np.zeros(max(1, n.value))
+    t = np.zeros(max(1, n.value))
+    _check(lib().sb_read_band_file(p, w.ctypes.data_as(_f64p), t.ctypes.data_as(_f64p), n.value, ctypes.byref(n)),
+           "sb_read_band_file")
+    return w[: n.value].copy(), t[: n.value].copy()
+
+
+def band_zeropoint_ab(wave, trans, max_spacing=5.0, rule=0):
+    """AB zero-point flux of band samples with the library's quadrature (host only)."""
+    w = np.ascontiguousarray(wave, np.float64)
+    t = np.ascontiguousarray(trans, np.float64)
+    zp = ctypes.c_double(0.0)
+    _check(lib().sb_band_zeropoint_ab(w.ctypes.data_as(_f64p), t.ctypes.data_as(_f64p), len(w), float(max_spacing),
+                                      int(rule), ctypes.byref(zp)), "sb_band_zeropoint_ab")
+    return zp.value
+
+
+def philox4x64_10(ctr, key):
+    """One block of the library's draws generator (host only)."""
+    c = (ctypes.c_uint64 * 4)(*[int(v) for v in ctr])
+    k = (ctypes.c_uint64 * 2)(*[int(v) for v in key])
+    o = (ctypes.c_uint64 * 4)()
+    lib().sb_philox4x64_10(c, k, o)
+    return [int(v) for v in o]
 
 
 def _dev(x, dtype, name):
@@ -291,6 +365,19 @@ class Context:
                                  ctypes.byref(bid)), "sb_add_band")
         self.n_bands += 1
         return bid.value
+
+    def add_band_file(self, path) -> int:
+        """Register the bandpass in a two-column text file (sb_add_band_file)."""
+        bid = ctypes.c_int32(-1)
+        _check(lib().sb_add_band_file(self._h, os.fsencode(path), ctypes.byref(bid)), "sb_add_band_file")
+        self.n_bands += 1
+        return bid.value
+
+    def zeropoint(self, band_id, magsys=SB_MAGSYS_AB) -> float:
+        """The band's zero-point flux (AB): m = -2.5 log10(f / zeropoint)."""
+        zp = ctypes.c_double(0.0)
+        _check(lib().sb_band_zeropoint(self._h, band_id, magsys, ctypes.byref(zp)), "sb_band_zeropoint")
+        return zp.value
 
     # ------------------------------------------------------------------ compute
     def _batch(self, z, t0, x0, x1, c, t, band, sn_offsets, broadcast, data, inv_sigma2, chi2):
@@ -397,14 +484,19 @@ class Context:
         _check(lib().sb_device_check(self._h, _stream(stream)), "sb_device_check")
 
     # ------------------------------------------------------------------ serving
-    def fit_submit(self, t, band, data, sigma, z, t0, x0, x1, c, free_mask=0) -> int:
-        """Queue one fit; free_mask: an OR of SB_FREE_* (0: all four parameters free)."""
+    def fit_submit(self, t, band, data, sigma, z, t0, x0, x1, c, free_mask=0, lower=None, upper=None) -> int:
+        """Queue one fit; free_mask: an OR of SB_FREE_* (0: all four parameters free); lower/upper:
+        bounds of (t0, x0, x1, c) for the L-BFGS-B solver (None: unbounded)."""
         t = np.ascontiguousarray(t, np.float32)
         band = np.ascontiguousarray(band, np.int32)
         data = np.ascontiguousarray(data, np.float32)
         sigma = np.ascontiguousarray(sigma, np.float32)
+        has = lower is not None or upper is not None
+        lo = np.full(4, -np.inf, np.float32) if lower is None else np.float32(lower)
+        hi = np.full(4, np.inf, np.float32) if upper is None else np.float32(upper)
         r = FitRequest(len(t), t.ctypes.data, band.ctypes.data, data.ctypes.data, sigma.ctypes.data,
-                       z, t0, x0, x1, c, free_mask)
+                       z, t0, x0, x1, c, free_mask, int(has), (ctypes.c_float * 4)(*lo.tolist()),
+                       (ctypes.c_float * 4)(*hi.tolist()))
         tk = ctypes.c_uint64(0)
         _check(lib().sb_fit_submit(self._h, ctypes.byref(r), ctypes.byref(tk)), "sb_fit_submit")
         return tk.value
@@ -423,7 +515,8 @@ class Context:
         _check(lib().sb_fit_cancel(self._h, ticket), "sb_fit_cancel")
 
     # ------------------------------------------------------------------ batch fits
-    def _fit_batch_desc(self, z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask):
+    def _fit_batch_desc(self, z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask, lower=None,
+                        upper=None):
         import torch
         for n, v in (("z", z), ("t0", t0), ("x0", x0), ("x1", x1), ("c", c), ("t", t), ("data", data),
                      ("inv_sigma2", inv_sigma2)):
@@ -443,8 +536,14 @@ class Context:
             _dev(free_mask, torch.int32, "free_mask")
             if free_mask.numel() != n_fit:
                 raise ValueError("free_mask must have n_fit elements")
+        for n, v in (("lower", lower), ("upper", upper)):
+            if v is not None:
+                _dev(v, torch.float32, n)
+                if v.numel() != 4 * n_fit:
+                    raise ValueError(f"{n} must have n_fit * 4 elements")
         return FitBatchDesc(n_fit, n_obs, _ptr(z), _ptr(t0), _ptr(x0), _ptr(x1), _ptr(c), _ptr(free_mask),
-                            _ptr(t), _ptr(band), _ptr(fit_offsets), _ptr(data), _ptr(inv_sigma2))
+                            _ptr(t), _ptr(band), _ptr(fit_offsets), _ptr(data), _ptr(inv_sigma2), _ptr(lower),
+                            _ptr(upper))
 
     @staticmethod
     def _fit_out_buffer(out, n_fit, device):
@@ -456,24 +555,62 @@ class Context:
             raise ValueError("out must hold n_fit sb_fit_out records (8 int32 words each)")
         return out
 
-    def fit_batch(self, z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask=None, out=None,
-                  stream=None):
+    def fit_batch(self, z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask=None, lower=None,
+                  upper=None, out=None, stream=None):
         """Fits every light curve of a device-resident batch (sb_fit_batch).  Returns the raw result
         records as an int32 tensor [n_fit, 8]; fit_results() unpacks them."""
-        d = self._fit_batch_desc(z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask)
+        d = self._fit_batch_desc(z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask, lower, upper)
         out = self._fit_out_buffer(out, d.n_fit, z.device)
         _check(lib().sb_fit_batch(self._h, ctypes.byref(d), _ptr(out), _stream(stream)), "sb_fit_batch")
         return out
 
-    def fit_batch_noalloc(self, z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask=None, out=None,
-                          stream=None):
+    def fit_batch_noalloc(self, z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask=None,
+                          lower=None, upper=None, out=None, stream=None):
         """As fit_batch, through sb_fit_batch_noalloc (fixed per-device state array, no allocation in
         the library; at most SB_FIT_NOALLOC_MAX fits; calls overlapping on one GPU race)."""
-        d = self._fit_batch_desc(z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask)
+        d = self._fit_batch_desc(z, t0, x0, x1, c, t, band, fit_offsets, data, inv_sigma2, free_mask, lower, upper)
         out = self._fit_out_buffer(out, d.n_fit, z.device)
         _check(lib().sb_fit_batch_noalloc(self._h, ctypes.byref(d), _ptr(out), _stream(stream)),
                "sb_fit_batch_noalloc")
         return out
+
+    # ------------------------------------------------------------------ nested sampling
+    def nested_sampling(self, priors, t, band, data, inv_sigma2, n_live=400, batch=4096, max_iter=100000,
+                        max_evals=50_000_000, dlogz=0.01, enlarge=1.5, seed=1, log_norm=0.0, stream=None):
+        """Nested sampling of one light curve's posterior (sb_nested_sampling).  priors: five (kind, a, b)
+        for z, t0, x0, x1, c; t, band, data, inv_sigma2: the device observation table.  Returns a dict
+        with logz, logz_err, information, n_iter, n_eval, n_batches, dead_* and live_* arrays."""
+        import torch
+        _dev(t, torch.float32, "t")
+        _dev(band, torch.int32, "band")
+        _dev(data, torch.float32, "data")
+        _dev(inv_sigma2, torch.float32, "inv_sigma2")
+        n_obs = t.numel()
+        if band.numel() != n_obs or data.numel() != n_obs or inv_sigma2.numel() != n_obs:
+            raise ValueError("the observation arrays must have one length")
+        cfg = NsConfig()
+        for d, (kind, a, b) in enumerate(priors):
+            cfg.prior[d] = Prior(int(kind), float(a), float(b))
+        cfg.n_live, cfg.batch, cfg.max_iter, cfg.max_evals = n_live, batch, max_iter, max_evals
+        cfg.dlogz, cfg.enlarge, cfg.seed, cfg.log_norm = dlogz, enlarge, seed, log_norm
+        dth = np.zeros((max_iter, 5))
+        dl = np.zeros(max_iter)
+        dw = np.zeros(max_iter)
+        dd = np.zeros(max_iter, np.int64)
+        lth = np.zeros((n_live, 5))
+        ll = np.zeros(n_live)
+        lw = np.zeros(n_live)
+        summ = NsSummary()
+        f64 = lambda a: a.ctypes.data_as(_f64p)
+        _check(lib().sb_nested_sampling(self._h, ctypes.byref(cfg), n_obs, _ptr(t), _ptr(band), _ptr(data),
+                                        _ptr(inv_sigma2), f64(dth), f64(dl), f64(dw),
+                                        dd.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), f64(lth), f64(ll), f64(lw),
+                                        ctypes.byref(summ), _stream(stream)), "sb_nested_sampling")
+        n = summ.n_iter
+        return {"logz": summ.logz, "logz_err": summ.logz_err, "information": summ.information, "n_iter": n,
+                "n_eval": summ.n_eval, "n_batches": summ.n_batches, "stopped_on_evals": bool(summ.stopped_on_evals),
+                "dead_theta": dth[:n], "dead_logl": dl[:n], "dead_logw": dw[:n], "dead_draw": dd[:n],
+                "live_theta": lth, "live_logl": ll, "live_logw": lw}
 
     def stats(self):
         s = Stats()

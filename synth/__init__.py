@@ -149,11 +149,12 @@ def _smooth_field(g: np.random.Generator, p, mu, n_modes=64):
     return np.sqrt(2.0 / n_modes) * np.cos(arg).sum(axis=0)
 
 
-def make_model(k: int = 0) -> Model:
-    """Synthetic SALT-shaped surfaces M0 > 0, M1 ~ 0.1*M0*N(0,1), cubic colour law."""
+def make_model(k: int = 0, n_wave: int = NWAVE) -> Model:
+    """Synthetic SALT-shaped surfaces M0 > 0, M1 ~ 0.1*M0*N(0,1), cubic colour law; n_wave columns
+    at 10 A from 2000 A (721: to 9200 A; 2001: to 22000 A, a near-infrared-wide grid)."""
     g = rng(k)
     p = PHASE0 + DPHASE * np.arange(NPHASE)
-    mu = WAVE0 + DWAVE * np.arange(NWAVE)
+    mu = WAVE0 + DWAVE * np.arange(n_wave)
     x = 14387.77 / mu                         # 1e4 K black-body shape
     planck = mu ** -5 / np.expm1(x)
     planck /= planck.max()
@@ -185,6 +186,24 @@ def make_bands(n_b: int, lo: float = 3500.0, hi: float = 9000.0, n_samples: int 
         tr[m] = np.exp(-0.5 * ((w[m] - core_hi) / edge_sigma) ** 2)
         bands.append(Band(wave=w, trans=tr))
     return bands
+
+
+def nir_bands() -> List[Band]:
+    """Stand-ins for near-infrared filters (Y, J, H-like supports), Gaussian-edged like make_bands."""
+    out = []
+    for lo, hi in ((9400.0, 11200.0), (11200.0, 13800.0), (14600.0, 18200.0)):
+        out += make_bands(1, lo, hi, n_samples=300, edge_sigma=40.0)
+    return out
+
+
+def write_band_file(path, band: Band, header: str = "") -> None:
+    """A two-column text file of the band's samples at full float64 precision (what a filter file
+    on disk looks like: comments, then wavelength and transmission per line)."""
+    with open(path, "w") as fh:
+        if header:
+            fh.write("".join(f"# {ln}\n" for ln in header.splitlines()))
+        for w, t in zip(band.wave, band.trans):
+            fh.write(f"{float(w)!r} {float(t)!r}\n")
 
 
 def tophat_band(a: float, b: float, n_samples: int = 200) -> Band:
@@ -239,10 +258,10 @@ def draw_params(g: np.random.Generator, n: int, zlo=0.01, zhi=1.0):
 
 
 def random_batch(k: int, n_sn: int, nobs_lo: int, nobs_hi: int, bands: List[Band], model: Model,
-                 phase_lo=-15.0, phase_hi=45.0, fixed_nobs=None) -> Batch:
+                 phase_lo=-15.0, phase_hi=45.0, fixed_nobs=None, zlo=0.01, zhi=1.0) -> Batch:
     """Uneven light curves: n_s ~ U{lo..hi}, rest phases ~ U(phase_lo, phase_hi), eligible bands."""
     g = rng(k)
-    z, t0, x0, x1, c = draw_params(g, n_sn)
+    z, t0, x0, x1, c = draw_params(g, n_sn, zlo, zhi)
     zf = f32r(z)
     ts, bs = [], []
     for s in range(n_sn):

@@ -89,7 +89,8 @@ def test_binding_structs_match_the_c_header(tmp_path):
         pytest.skip("no C compiler")
     pairs = [("sb_model_desc", sb.ModelDesc), ("sb_config", sb.Config), ("sb_batch", sb.Batch),
              ("sb_fit_request", sb.FitRequest), ("sb_fit_result", sb.FitResult), ("sb_stats_t", sb.Stats),
-             ("sb_fit_batch_desc", sb.FitBatchDesc), ("sb_fit_out", sb.FitOut)]
+             ("sb_fit_batch_desc", sb.FitBatchDesc), ("sb_fit_out", sb.FitOut), ("sb_prior", sb.Prior),
+             ("sb_ns_config", sb.NsConfig), ("sb_ns_summary", sb.NsSummary)]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "saltbf.h"', "int main(void) {"]
     for cname, py in pairs:
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
