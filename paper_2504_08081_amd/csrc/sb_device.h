@@ -269,10 +269,15 @@ __device__ inline void cell_taps(typename ModeInfo<MODE>::V (&C)[4], const Lds& 
   }
 }
 
-// v from the next lane down (lane L receives lane L - 1; lane 0 its own value).
-__device__ inline float up1(float v) { return __shfl_up(v, 1, WAVE); }
-__device__ inline float2 up1(float2 v) { return make_float2(up1(v.x), up1(v.y)); }
-__device__ inline float4 up1(float4 v) { return make_float4(up1(v.x), up1(v.y), up1(v.z), up1(v.w)); }
+// v plus w of the next lane down: lane L adds lane L - 1's w, lane 0 adds 0 (one DPP wave
+// shift fused into the add).
+__device__ inline float add_up1(float v, float w) {
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(w), 0x138, 0xF, 0xF, true));
+}
+__device__ inline float2 add_up1(float2 v, float2 w) { return make_float2(add_up1(v.x, w.x), add_up1(v.y, w.y)); }
+__device__ inline float4 add_up1(float4 v, float4 w) {
+  return make_float4(add_up1(v.x, w.x), add_up1(v.y, w.y), add_up1(v.z, w.z), add_up1(v.w, w.w));
+}
 
 // Surface nodes (M0, M1) of the lane's row in CW consecutive columns: buffer
 // loads with the lane's row offset loff in a vector register and the column's
@@ -545,8 +550,8 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
   //     pass starting at column b takes column b + L and the cell just above
   //     it, j_lo + b + L + 1, and sums the four taps of that cell's points
   //     (each point read once).  Column b + L needs tap t of the cell t below
-  //     that one, held by lane L - t: G = C0 + up(C1 + up(C2 + up(C3))).
-  //     Passes start 3 columns early and advance by WAVE - 3, so every tap a
+  //     that one, held by lane L - t: G = C0 + up(C1 + up(C2 + up(C3))), each
+  //     "+ up" one DPP-shifted add.  Passes start 3 columns early and advance by WAVE - 3, so every tap a
   //     written column needs comes from a lane of the same pass.
   //     Only a window that reaches the grid's first or last cell can hold an
   //     edge cell, so other windows take the branch without the edge weights.
@@ -563,9 +568,10 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
       else
         cell_taps<MODE, false>(C, L, k0, k1, false, c);
     }
-    V g = C[2] + up1(C[3]);
-    g = C[1] + up1(g);
-    g = C[0] + up1(g);
+    // lanes 0..2 write nothing, so the zero shifted into lane 0 never reaches a written column
+    V g = add_up1(C[2], C[3]);
+    g = add_up1(C[1], g);
+    g = add_up1(C[0], g);
     if (lane >= 3 && col < J) Gv[col] = g;
   }
   wave_sync();
