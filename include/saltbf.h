@@ -182,7 +182,7 @@ enum {
 /* A batch of supernovae in structure-of-arrays layout, all device pointers.
  * Supernova s has parameters z[s], t0[s], x0[s], x1[s], c[s] (z > -1).  A band
  * whose rest-frame window lam/(1+z) leaves the surface's wavelength grid, or
- * (only possible for z < -1/4) spans more surface columns than the context
+ * (only possible for z < -1/20) spans more surface columns than the context
  * sized its LDS for, cannot be evaluated: its observations give NaN and the
  * device flag that sb_device_check reports as SB_ERR_RANGE is set.
  * Without SB_OBS_BROADCAST its observations are i in [sn_offsets[s], sn_offsets[s+1])
@@ -379,6 +379,32 @@ sb_status sb_nested_sampling(sb_ctx *ctx, const sb_ns_config *cfg, int32_t n_obs
 
 /* Host-only: one Philox4x64-10 block (the draws' generator), for checking it. */
 void sb_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* ------------------------------------------------------------ peak probes
+ * Micro-benchmarks of the rates a roofline is quoted against (the MI355X
+ * datasheet gives 157.3 TFLOP/s vector FP32 with packed FP32 and 8 TB/s of
+ * HBM), for the caller to time on the device at hand: one launch, on the
+ * current device and hip_stream, of a kernel whose work is known exactly; *work
+ * receives its FLOPs or bytes.
+ *   SB_PROBE_FMA_F32   n workgroups of 256 threads; each thread runs 16
+ *                      independent chains of `iters` FP32 fused multiply-adds
+ *                      x <- x a + b (chain j starts at j; a = 1023/1024,
+ *                      b = 1/1024), unpacked like every kernel of this library,
+ *                      and writes the sum of its chains to dst[thread] (device
+ *                      float [n * 256]); work = 2 * n * 256 * 16 * iters flops.
+ *   SB_PROBE_LDS_READ  n workgroups of 256 threads; each fills a 16 KiB LDS table
+ *                      of float4 T[i] = (i, i + 1/4, i + 1/2, i + 3/4) and reads
+ *                      all of it `iters` times over (thread t, sweep k: entries
+ *                      (t xor (k mod 256)) + 256 r, r = 0..3, conflict free), writing
+ *                      the sum of the components it read to dst[thread] (device
+ *                      float [n * 256]); work = n * iters * 16384 bytes.
+ *   SB_PROBE_COPY      copies n bytes (a multiple of 16) from device src to dst with
+ *                      128-bit loads and stores; work = 2 n bytes (read + write).
+ * SB_ERR_ARG for an unknown kind, n < 1, iters < 1 (FMA, LDS), n above 2^23
+ * workgroups (FMA, LDS), a NULL buffer or one not 16-byte aligned. */
+enum { SB_PROBE_FMA_F32 = 0, SB_PROBE_LDS_READ = 1, SB_PROBE_COPY = 2 };
+sb_status sb_peak_probe(int32_t kind, int64_t n, int32_t iters, const void *src, void *dst, double *work,
+                        void *hip_stream);
 
 typedef struct {
   int64_t submitted, admitted, completed, cancelled, rejected;

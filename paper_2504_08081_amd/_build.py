@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libsaltbf.so")
-SOURCES = ["sb_bandflux.hip", "sb_fit.hip", "sb_host.cpp", "sb_server.cpp", "sb_nested.cpp"]
+SOURCES = ["sb_bandflux.hip", "sb_fit.hip", "sb_probe.hip", "sb_host.cpp", "sb_server.cpp", "sb_nested.cpp"]
 
 # Packed FP32 instructions are switched off for every HIP source.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -213,12 +213,26 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
   }
 }
 
+// Workgroup `bid` of `n` goes to XCD bid mod N_XCD (the dispatcher hands workgroups
+// to the XCDs in turn).  This maps the workgroups so that XCD x takes the
+// contiguous items [x q + min(x, r), ...) (q = n div N_XCD, r = n mod N_XCD, the
+// first r XCDs one more) in order: neighbouring supernovae share the cache lines
+// at the ends of their observation ranges, which are then fetched into one L2
+// instead of two.  A bijection of [0, n) for any n.
+__device__ inline int xcd_item(int bid, int n) {
+  const int q = n / N_XCD, r = n % N_XCD, x = bid % N_XCD;
+  return x * q + min(x, r) + bid / N_XCD;
+}
+
 template <int MODE, bool BCAST, int NW>
-__global__ __launch_bounds__(NW * WAVE) void k_sn(KModel m, KTables tb, KBatch b) {
+// At most 102 VGPRs (five waves per SIMD): the adjoint then takes 93 without
+// spilling, and six of its three-wave workgroups fit a CU's registers and LDS
+// (4% faster on 4,096 supernovae than five at 116 VGPRs).  The forward takes 55.
+__global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(5))) void k_sn(KModel m, KTables tb, KBatch b) {
   extern __shared__ __align__(16) char smem[];
   __shared__ SnShared S;
   const Lds L = lds_carve<MODE, NW>(smem, m, tb, uni((int)(threadIdx.x / WAVE)));
-  sn_body<MODE, BCAST, NW>(m, tb, b, blockIdx.x, L, S);
+  sn_body<MODE, BCAST, NW>(m, tb, b, xcd_item(blockIdx.x, gridDim.x), L, S);
 }
 
 size_t lds_bytes(const KModel& m, int max_pts, int jcap, bool adj) {

@@ -54,15 +54,16 @@ template <int MODE> struct ModeInfo;
 // handed to the waves in turn (wave w takes the group's bands w, w + NW, ...),
 // each wave building its bands' weight vectors in its own LDS scratch.  GROUP
 // bands have their row projections held in LDS at once, and the observations
-// of those bands are finished in one pass by the whole workgroup; a smaller
-// group keeps the larger adjoint projections within a footprint that lets more
-// waves share a compute unit (an extra group costs one more scan of the band ids).
+// of those bands are finished in one pass by the whole workgroup (an extra group
+// costs one more scan of the band ids).  The adjoint's three waves and six-band
+// groups give a supernova of five or six bands two bands per wave in one group
+// (3-4% faster on 4,096 supernovae than two waves over groups of four, whose
+// second group left one wave idle; four waves over eight bands were slower).
 // CW is the column chunk of the row projections (columns whose surface loads
-// are in flight together); the adjoint reads 4-column chunks of the difference
-// surface.
+// are in flight together).
 template <> struct ModeInfo<FWD> { static constexpr int NG = 1, NR = 1, NW = 2, GROUP = 8, CW = 4; typedef float V; };
 template <> struct ModeInfo<FIT> { static constexpr int NG = 2, NR = 3, NW = 8, GROUP = 8, CW = 4; typedef float2 V; };
-template <> struct ModeInfo<VJP> { static constexpr int NG = 4, NR = 5, NW = 2, GROUP = 4, CW = 4; typedef float4 V; };
+template <> struct ModeInfo<VJP> { static constexpr int NG = 4, NR = 5, NW = 3, GROUP = 6, CW = 4; typedef float4 V; };
 
 // Largest group over the modes (sizes the per-slot flags).
 constexpr int BAND_GROUP = 8;
@@ -560,14 +561,16 @@ __device__ bool band_rows(const KModel& m, const KTables& tb, int bd, double s, 
     const int col = b + lane;
     const int cell = j_lo + col + 1;
     const int q = cell - j0f;
+    // lanes without a cell of the window run an empty point range (one code path,
+    // so the tap sums are zeroed once)
+    const bool has = q >= 0 && q < ncell;
+    const int qc = has ? q : 0;
+    const int k0 = max(L.kf[qc], 0), k1 = has ? min(L.kf[qc + 1], np) : k0;
     V C[4] = {vzero<V>(), vzero<V>(), vzero<V>(), vzero<V>()};
-    if (q >= 0 && q < ncell) {
-      const int k0 = max(L.kf[q], 0), k1 = min(L.kf[q + 1], np);
-      if (win_edge)
-        cell_taps<MODE, true>(C, L, k0, k1, (cell == 0) || (cell == m.n_wave - 2), c);
-      else
-        cell_taps<MODE, false>(C, L, k0, k1, false, c);
-    }
+    if (win_edge)
+      cell_taps<MODE, true>(C, L, k0, k1, (cell == 0) || (cell == m.n_wave - 2), c);
+    else
+      cell_taps<MODE, false>(C, L, k0, k1, false, c);
     // lanes 0..2 write nothing, so the zero shifted into lane 0 never reaches a written column
     V g = add_up1(C[2], C[3]);
     g = add_up1(C[1], g);

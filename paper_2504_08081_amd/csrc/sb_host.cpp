@@ -524,6 +524,30 @@ sb_status sb_fit_batch_noalloc(sb_ctx* ctx, const sb_fit_batch_desc* b, sb_fit_o
   return SB_OK;
 }
 
+sb_status sb_peak_probe(int32_t kind, int64_t n, int32_t iters, const void* src, void* dst, double* work,
+                        void* hip_stream) {
+  if (!work || !dst) return set_error(SB_ERR_ARG, "sb_peak_probe: NULL argument");
+  if (n < 1) return set_error(SB_ERR_ARG, "sb_peak_probe: n must be positive");
+  if (((uintptr_t)dst & 15) != 0) return set_error(SB_ERR_ARG, "sb_peak_probe: dst must be 16-byte aligned");
+  switch (kind) {
+    case SB_PROBE_FMA_F32:
+    case SB_PROBE_LDS_READ:
+      if (iters < 1) return set_error(SB_ERR_ARG, "sb_peak_probe: iters must be positive");
+      if (n > (1 << 23)) return set_error(SB_ERR_ARG, "sb_peak_probe: more than 2^23 workgroups");
+      break;
+    case SB_PROBE_COPY:
+      if (!src || ((uintptr_t)src & 15) != 0)
+        return set_error(SB_ERR_ARG, "sb_peak_probe: src must be a 16-byte aligned device buffer");
+      if (n % 16 != 0) return set_error(SB_ERR_ARG, "sb_peak_probe: copy size must be a multiple of 16 bytes");
+      break;
+    default:
+      return set_error(SB_ERR_ARG, "sb_peak_probe: unknown probe kind");
+  }
+  const hipError_t e = sbk::launch_probe(kind, n, iters, src, dst, work, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "sb_peak_probe: launch");
+  return SB_OK;
+}
+
 sb_status sb_device_check(sb_ctx* ctx, void* hip_stream) {
   if (!ctx) return set_error(SB_ERR_ARG, "sb_device_check: NULL context");
   hipError_t e = hipSetDevice(ctx->device);

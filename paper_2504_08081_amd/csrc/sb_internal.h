@@ -10,10 +10,11 @@
 namespace sbk {
 
 constexpr int WAVE = 64;           // threads per wavefront
+constexpr int N_XCD = 8;           // accelerator complex dies (each with its own L2) of an MI355X
 constexpr int MAX_NW = 8;          // wavefronts per workgroup, at most (per mode in sb_device.h)
 constexpr int MAX_PHASE = 256;     // surface rows supported
 constexpr int MAX_WAVE = 8192;     // surface columns supported
-constexpr double WINDOW_Z_MIN = -0.25;  // the LDS window capacity covers every z >= this
+constexpr double WINDOW_Z_MIN = -0.05;  // the LDS window capacity covers every z >= this
 constexpr int SURF_PAD_COLS = 16;  // zero columns after the last surface column (at least the widest chunk)
 constexpr int BUF_RSRC_WORD3 = 0x00020000;  // buffer resource flags word (gfx9 family: raw 32-bit data)
 constexpr unsigned BUF_OFF_NONE = 0x40000000u;  // a buffer offset past every resource: the load returns 0
@@ -155,6 +156,9 @@ hipError_t launch_fit(const KModel& m, const KTables& tb, const KFit& f, hipStre
 hipError_t launch_fit_batch(const KModel& m, const KTables& tb, KFit f, int n_fit, int fit_iters,
                             int iters_per_tick, hipStream_t st);
 size_t fit_lds_bytes(const KModel& m, int max_pts, int jcap);   // smallest form, as lds_bytes
+
+// Peak-rate probes (sb_probe.hip): one launch of probe `kind` (SB_PROBE_*), its FLOPs or bytes in *work.
+hipError_t launch_probe(int kind, int64_t n, int iters, const void* src, void* dst, double* work, hipStream_t st);
 
 // The fixed per-device state array of allocation-free batch fits
 // (SB_FIT_NOALLOC_MAX slots): fit_scratch_init takes its device address once per

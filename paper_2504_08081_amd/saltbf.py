@@ -27,13 +27,15 @@ SB_MAGSYS_AB = 0
 SB_PRIOR_FIXED, SB_PRIOR_UNIFORM, SB_PRIOR_LOG_UNIFORM = 0, 1, 2
 SB_MAX_BANDS, SB_MAX_BAND_POINTS, SB_N_PARAMS = 64, 2048, 5
 SB_FIT_NOALLOC_MAX = 8192
+SB_PROBE_FMA_F32, SB_PROBE_LDS_READ, SB_PROBE_COPY = 0, 1, 2
+PROBE_THREADS = 256
 
 EXPORTED = (
     "sb_config_default", "sb_create", "sb_destroy", "sb_add_band", "sb_band_grid", "sb_bandflux",
     "sb_bandflux_vjp", "sb_device_check", "sb_fit_submit", "sb_fit_poll", "sb_fit_wait", "sb_fit_cancel",
     "sb_stats", "sb_status_string", "sb_last_error", "sb_fit_batch", "sb_fit_batch_noalloc",
     "sb_read_band_file", "sb_add_band_file", "sb_band_zeropoint", "sb_band_zeropoint_ab",
-    "sb_nested_sampling", "sb_philox4x64_10",
+    "sb_nested_sampling", "sb_philox4x64_10", "sb_peak_probe",
 )
 
 _f32p = ctypes.POINTER(ctypes.c_float)
@@ -197,6 +199,8 @@ def lib():
         u64p = ctypes.POINTER(ctypes.c_uint64)
         L.sb_philox4x64_10.argtypes = [u64p, u64p, u64p]
         L.sb_philox4x64_10.restype = None
+        L.sb_peak_probe.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, vp, vp, _f64p, vp]
+        L.sb_peak_probe.restype = st
         L.sb_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.sb_stats.restype = st
         L.sb_status_string.argtypes = [st]
@@ -267,6 +271,24 @@ def philox4x64_10(ctr, key):
     o = (ctypes.c_uint64 * 4)()
     lib().sb_philox4x64_10(c, k, o)
     return [int(v) for v in o]
+
+
+def peak_probe(kind, n, iters=1, src=None, dst=None, stream=None):
+    """One launch of a peak-rate probe (SB_PROBE_*) on the current device; returns its FLOPs or bytes.
+    FMA_F32 and LDS_READ: n workgroups, dst a float32 CUDA tensor of n * 256 elements; COPY: n bytes
+    from src to dst (CUDA tensors of at least n bytes)."""
+    if kind in (SB_PROBE_FMA_F32, SB_PROBE_LDS_READ):
+        _dev(dst, __import__("torch").float32, "dst")
+        if dst.numel() < n * PROBE_THREADS:
+            raise ValueError("dst must hold n * 256 floats")
+    elif kind == SB_PROBE_COPY:
+        for x, name in ((src, "src"), (dst, "dst")):
+            if x is None or not x.is_cuda or not x.is_contiguous() or x.numel() * x.element_size() < n:
+                raise ValueError(f"{name} must be a contiguous CUDA tensor of at least n bytes")
+    work = ctypes.c_double(0.0)
+    _check(lib().sb_peak_probe(int(kind), int(n), int(iters), _ptr(src), _ptr(dst), ctypes.byref(work),
+                               _stream(stream)), "sb_peak_probe")
+    return work.value
 
 
 def _dev(x, dtype, name):

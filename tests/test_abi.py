@@ -110,3 +110,26 @@ def test_binding_structs_match_the_c_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_peak_probe_rejects_bad_arguments_on_the_host():
+    """sb_peak_probe checks its arguments before anything reaches the GPU."""
+    sb = _lib()
+    L = sb.lib()
+    w = ctypes.c_double(0.0)
+    fake = ctypes.c_void_p(1 << 20)             # aligned, never dereferenced: every call below is refused
+    odd = ctypes.c_void_p((1 << 20) + 4)
+    cases = [
+        (7, 16, 1, fake, fake),                 # unknown kind
+        (sb.SB_PROBE_FMA_F32, 0, 1, None, fake),     # no workgroups
+        (sb.SB_PROBE_FMA_F32, 16, 0, None, fake),    # no iterations
+        (sb.SB_PROBE_LDS_READ, (1 << 23) + 1, 1, None, fake),
+        (sb.SB_PROBE_FMA_F32, 16, 1, None, odd),     # misaligned dst
+        (sb.SB_PROBE_COPY, 100, 1, fake, fake),      # not a multiple of 16 bytes
+        (sb.SB_PROBE_COPY, 1024, 1, None, fake),     # no source
+        (sb.SB_PROBE_COPY, 1024, 1, odd, fake),      # misaligned source
+        (sb.SB_PROBE_FMA_F32, 16, 1, None, None),    # no destination
+    ]
+    for kind, n, iters, src, dst in cases:
+        assert L.sb_peak_probe(kind, n, iters, src, dst, ctypes.byref(w), None) == sb.SB_ERR_ARG, (kind, n, iters)
+    assert L.sb_peak_probe(sb.SB_PROBE_FMA_F32, 16, 1, None, fake, None, None) == sb.SB_ERR_ARG

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import torch_or_skip
+from gpu_util import fit_resolution, torch_or_skip
 
 pytestmark = pytest.mark.gpu
 
@@ -141,8 +141,9 @@ def test_fits_with_held_parameters(sb, o6, model, bands6, requests, mask):
 
 
 def test_fits_with_single_wave_workgroups(sb, o6, model, bands6, requests):
-    """A 12 KiB LDS limit makes the fit kernel run one wave per fit; fits still match the oracle."""
-    ctx = sb.Context.from_model(model, bands6, lds_limit_bytes=12 * 1024)
+    """A 15 KiB LDS limit makes the fit kernel run one wave per fit (its eight-wave layout takes 34 KiB);
+    fits still match the oracle."""
+    ctx = sb.Context.from_model(model, bands6, lds_limit_bytes=15 * 1024)
     items = requests[:6]
     res = run_all(ctx, items)
     fo = oracle.FitOracle(o6)
@@ -306,7 +307,8 @@ def test_poll_and_ticket_lifecycle(sb, model, bands6, requests):
 def test_lbfgsb_served_fits_match_oracle(sb, o6, model, bands6, requests):
     """A server running the L-BFGS-B solver: 24 fits, every third with a box on (x1, c) whose c
     upper bound excludes the unconstrained optimum, against the FP64 L-BFGS-B fit with the same
-    bounds (parameters within 1e-2 of their uncertainty, chi2 within 1e-5)."""
+    bounds (parameters within the fit's FP32 resolution, at least 1e-2 of their uncertainty; chi2
+    within 1e-5)."""
     ctx = sb.Context.from_model(model, bands6, solver=sb.SB_SOLVER_LBFGSB)
     fo = oracle.FitOracle(o6)
     items = requests[:24]
@@ -335,7 +337,9 @@ def test_lbfgsb_served_fits_match_oracle(sb, o6, model, bands6, requests):
         _, H, _ = fo.evaluate(single_batch(r), r.z, q64, d, w)
         dev = np.abs(qg - q64) / np.sqrt(np.diag(np.linalg.inv(H)))
         worst = max(worst, dev.max())
-        assert dev.max() <= 2 * THETA_SIGMA_TOL, (dev, g.as_dict())   # see test_gpu_fit_batch
+        # held to the fit's own FP32 resolution (see test_gpu_fit_batch), THETA_SIGMA_TOL at least
+        tol = max(THETA_SIGMA_TOL, fit_resolution(o6.bandflux(single_batch(r, th)), d, w, ref["chi2"]))
+        assert dev.max() <= tol, (dev, tol, g.as_dict())
         assert abs(g.chi2 - ref["chi2"]) <= CHI2_TOL * ref["chi2"]
         if bd is not None:
             assert np.float32(g.c) == bd[1][3]
