@@ -516,6 +516,10 @@ def main():
         d_sw, wall_sw = time_launches(torch, ctx.prepare_bandflux(**P, t=t_o, band=b_o, broadcast=True, chi2=True,
                                                                   data=D_s["data"], inv_sigma2=D_s["w"], out=chi),
                                       reps, 1)
+        chi_ps = torch.empty(smp.n_sn, device="cuda")
+        d_ps, _ = time_launches(torch, ctx.prepare_bandflux(**P, t=t_o, band=b_o, broadcast="persistent", chi2=True,
+                                                             data=D_s["data"], inv_sigma2=D_s["w"], out=chi_ps),
+                                reps, 1)
         n = smp.n_sn
         tt, bb = t_o.repeat(n), b_o.repeat(n)
         off = torch.arange(0, (n + 1) * no, no, dtype=torch.int32, device="cuda")
@@ -524,13 +528,14 @@ def main():
         d_pl, wall_pl = time_launches(torch, ctx.prepare_bandflux(**P, t=tt, band=bb, sn_offsets=off, chi2=True,
                                                                   data=dd, inv_sigma2=ww, out=chi_pl), reps, 1)
         ctx.device_check()
-        same = bool(torch.equal(chi, chi_pl))
+        same = bool(torch.equal(chi, chi_pl)) and bool(torch.equal(chi, chi_ps))
         del tt, bb, off, dd, ww
         evals = n * no
         result["sweep"] = {"samples": n, "obs": no, "broadcast_evals_per_s": evals / (d_sw.mean() * 1e-3),
+                           "persistent_evals_per_s": evals / (d_ps.mean() * 1e-3),
                            "plain_evals_per_s": evals / (d_pl.mean() * 1e-3),
-                           "broadcast_ms": float(d_sw.mean()), "plain_ms": float(d_pl.mean()),
-                           "bitwise_equal": same}
+                           "broadcast_ms": float(d_sw.mean()), "persistent_ms": float(d_ps.mean()),
+                           "plain_ms": float(d_pl.mean()), "bitwise_equal": same}
         log(f"sweep: {result['sweep']}")
 
     if "big" in legs:

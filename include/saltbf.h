@@ -175,8 +175,12 @@ sb_status sb_band_zeropoint_ab(const double *wave, const double *trans, int32_t 
 /* Batch flags. */
 enum {
   SB_OBS_BROADCAST = 1,  /* one observation table [n_obs] shared by all n_sn parameter samples */
-  SB_OUT_CHI2 = 2        /* sb_bandflux: write chi2 per supernova instead of fluxes;
+  SB_OUT_CHI2 = 2,       /* sb_bandflux: write chi2 per supernova instead of fluxes;
                             sb_bandflux_vjp: cotangent = d chi2 / d f = 2 (f - data) inv_sigma2 */
+  SB_PERSISTENT = 4      /* with SB_OBS_BROADCAST only (else SB_ERR_ARG): a persistent launch of a fixed
+                            grid of G workgroups (16 per workgroup the device holds at once, at most
+                            one per sample), workgroup g taking samples g, g + G, ..., instead of one
+                            workgroup per sample; every result is bitwise the same */
 };
 
 /* A batch of supernovae in structure-of-arrays layout, all device pointers.
@@ -399,7 +403,8 @@ void sb_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out
  *                      the sum of the components it read to dst[thread] (device
  *                      float [n * 256]); work = n * iters * 16384 bytes.
  *   SB_PROBE_COPY      copies n bytes (a multiple of 16) from device src to dst with
- *                      128-bit loads and stores; work = 2 n bytes (read + write).
+ *                      non-temporal 128-bit loads and stores, one per thread;
+ *                      work = 2 n bytes (read + write).
  * SB_ERR_ARG for an unknown kind, n < 1, iters < 1 (FMA, LDS), n above 2^23
  * workgroups (FMA, LDS), a NULL buffer or one not 16-byte aligned. */
 enum { SB_PROBE_FMA_F32 = 0, SB_PROBE_LDS_READ = 1, SB_PROBE_COPY = 2 };

@@ -235,6 +235,23 @@ __global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(5))) 
   sn_body<MODE, BCAST, NW>(m, tb, b, xcd_item(blockIdx.x, gridDim.x), L, S);
 }
 
+// A sweep as a persistent launch: workgroup g evaluates samples g, g + G, ...
+// (G = the grid), each exactly as k_sn's workgroup for that sample would; the
+// loop bounds are uniform, and a barrier separates one sample's last reads of
+// the shared tables from the next sample's scan.
+template <int MODE, int NW>
+__global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(5))) void k_sweep(KModel m, KTables tb,
+                                                                                           KBatch b) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ SnShared S;
+  const Lds L = lds_carve<MODE, NW>(smem, m, tb, uni((int)(threadIdx.x / WAVE)));
+  const int n = uni(b.n_sn), step = uni((int)gridDim.x);
+  for (int s = uni((int)blockIdx.x); s < n; s += step) {
+    sn_body<MODE, true, NW>(m, tb, b, s, L, S);
+    __syncthreads();
+  }
+}
+
 size_t lds_bytes(const KModel& m, int max_pts, int jcap, bool adj) {
   return adj ? lds_layout_bytes<VJP>(m.n_phase, max_pts, jcap, 1)
              : lds_layout_bytes<FWD>(m.n_phase, max_pts, jcap, 1);
@@ -263,6 +280,39 @@ static hipError_t launch_one(const KModel& m, const KTables& tb, const KBatch& b
   return launch_nw<MODE, BCAST, 1>(m, tb, b, lds_layout_bytes<MODE>(m.n_phase, tb.max_pts, tb.jcap, 1), st);
 }
 
+// A persistent sweep with k_sn's workgroup shape for the mode (so each sample's
+// results are bitwise those of the one-workgroup-per-sample launch), never more
+// workgroups than samples.  Samples differ in cost (z sets each band's window),
+// so a static stride needs spare workgroups to balance: on 1,048,576 samples
+// one workgroup per resident slot took 16.6 ms, PERSIST_ROUNDS = 16 per slot
+// 13.5 ms, against 13.2 ms for one workgroup per sample (the hardware
+// dispatcher balances dynamically and its per-workgroup cost is small).
+constexpr int PERSIST_ROUNDS = 16;
+
+template <int MODE, int NW>
+static hipError_t launch_sweep_nw(const KModel& m, const KTables& tb, const KBatch& b, size_t lds, hipStream_t st) {
+  hipError_t e = prep_lds(k_sweep<MODE, NW>, lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, n_cu = 0, per_cu = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<MODE, NW>, NW * WAVE, lds);
+  if (e != hipSuccess) return e;
+  const long long slots = (long long)(per_cu > 0 ? per_cu : 1) * (n_cu > 0 ? n_cu : 1) * PERSIST_ROUNDS;
+  const int grid = (int)(slots < b.n_sn ? slots : b.n_sn);
+  hipLaunchKernelGGL((k_sweep<MODE, NW>), dim3(grid), dim3(NW * WAVE), lds, st, m, tb, b);
+  return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_sweep(const KModel& m, const KTables& tb, const KBatch& b, hipStream_t st) {
+  constexpr int NW = ModeInfo<MODE>::NW;
+  const size_t lds = lds_layout_bytes<MODE>(m.n_phase, tb.max_pts, tb.jcap, NW);
+  if (lds <= (size_t)tb.lds_limit) return launch_sweep_nw<MODE, NW>(m, tb, b, lds, st);
+  return launch_sweep_nw<MODE, 1>(m, tb, b, lds_layout_bytes<MODE>(m.n_phase, tb.max_pts, tb.jcap, 1), st);
+}
+
 // Forward calls that return fluxes only may use any number of waves per
 // supernova: each observation's flux comes from its band's projections, built
 // by one wave whatever the workgroup size, so the results are bit for bit the
@@ -280,6 +330,7 @@ constexpr int FEW_SN_VJP_NW = ModeInfo<VJP>::GROUP;
 
 hipError_t launch_sn(bool adj, const KModel& m, const KTables& tb, const KBatch& b, hipStream_t st) {
   const bool bc = (b.flags & SB_OBS_BROADCAST) != 0;
+  if (bc && (b.flags & SB_PERSISTENT)) return adj ? launch_sweep<VJP>(m, tb, b, st) : launch_sweep<FWD>(m, tb, b, st);
   if (adj && !bc && b.n_sn <= FEW_SN) {
     const size_t lds = lds_layout_bytes<VJP>(m.n_phase, tb.max_pts, tb.jcap, FEW_SN_VJP_NW);
     if (lds <= (size_t)tb.lds_limit) return launch_nw<VJP, false, FEW_SN_VJP_NW>(m, tb, b, lds, st);

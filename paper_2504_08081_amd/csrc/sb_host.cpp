@@ -390,7 +390,9 @@ static sb_status check_batch(const sb_ctx* ctx, const sb_batch* b, const char* w
   if (b->n_sn > (1 << 24) - 1) return set_error(SB_ERR_ARG, w + ": more than 2^24 - 1 supernovae in one call");
   if ((b->flags & SB_OBS_BROADCAST) && (int64_t)b->n_sn * b->n_obs > ((int64_t)1 << 40))
     return set_error(SB_ERR_ARG, w + ": broadcast output too large");
-  if (b->flags & ~(SB_OBS_BROADCAST | SB_OUT_CHI2)) return set_error(SB_ERR_ARG, w + ": unknown flags");
+  if (b->flags & ~(SB_OBS_BROADCAST | SB_OUT_CHI2 | SB_PERSISTENT)) return set_error(SB_ERR_ARG, w + ": unknown flags");
+  if ((b->flags & SB_PERSISTENT) && !(b->flags & SB_OBS_BROADCAST))
+    return set_error(SB_ERR_ARG, w + ": SB_PERSISTENT needs SB_OBS_BROADCAST");
   if (ctx->n_bands == 0) return set_error(SB_ERR_STATE, w + ": no band registered");
   if (b->n_sn > 0 && (!b->z || !b->t0 || !b->x0 || !b->x1 || !b->c))
     return set_error(SB_ERR_ARG, w + ": NULL parameter array");

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libsaltbf.so")
 SB_OK, SB_PENDING, SB_CANCELLED, SB_FIT_DIVERGED = 0, 1, 2, 3
 SB_ERR_ARG, SB_ERR_RANGE, SB_ERR_DEVICE, SB_ERR_NOMEM = -1, -2, -3, -4
 SB_ERR_BUDGET, SB_ERR_STATE, SB_ERR_NOTFOUND = -5, -6, -7
-SB_OBS_BROADCAST, SB_OUT_CHI2 = 1, 2
+SB_OBS_BROADCAST, SB_OUT_CHI2, SB_PERSISTENT = 1, 2, 4
 SB_QUAD_TRAPEZOID, SB_QUAD_MIDPOINT = 0, 1
 SB_FREE_T0, SB_FREE_X0, SB_FREE_X1, SB_FREE_C, SB_FREE_ALL = 1, 2, 4, 8, 15
 SB_SOLVER_LM, SB_SOLVER_LBFGSB = 0, 1
@@ -422,14 +422,19 @@ class Context:
             _dev(inv_sigma2, torch.float32, "inv_sigma2")
             if data.numel() != n_obs or inv_sigma2.numel() != n_obs:
                 raise ValueError("data / inv_sigma2 must have n_obs elements")
-        flags = (SB_OBS_BROADCAST if broadcast else 0) | (SB_OUT_CHI2 if chi2 else 0)
+        if broadcast not in (False, True, "persistent"):
+            raise ValueError('broadcast must be False, True or "persistent"')
+        flags = ((SB_OBS_BROADCAST if broadcast else 0) | (SB_PERSISTENT if broadcast == "persistent" else 0)
+                 | (SB_OUT_CHI2 if chi2 else 0))
         return Batch(n_sn, n_obs, flags, _ptr(z), _ptr(t0), _ptr(x0), _ptr(x1), _ptr(c), _ptr(t), _ptr(band),
                      None if broadcast else _ptr(sn_offsets), _ptr(data) if chi2 else None,
                      _ptr(inv_sigma2) if chi2 else None)
 
     def bandflux(self, z, t0, x0, x1, c, t, band, sn_offsets=None, *, broadcast=False, data=None,
                  inv_sigma2=None, chi2=False, out=None, stream=None):
-        """Fluxes [n_obs] ([n_sn, n_obs] with broadcast), or chi2 [n_sn] with chi2=True."""
+        """Fluxes [n_obs] ([n_sn, n_obs] with broadcast), or chi2 [n_sn] with chi2=True.  broadcast:
+        False (CSR batch), True (one observation table for all samples, a workgroup per sample) or
+        "persistent" (the same sweep as a persistent launch; bitwise the same results)."""
         import torch
         b = self._batch(z, t0, x0, x1, c, t, band, sn_offsets, broadcast, data, inv_sigma2, chi2)
         shape = (b.n_sn,) if chi2 else ((b.n_sn, b.n_obs) if broadcast else (b.n_obs,))

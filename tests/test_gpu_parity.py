@@ -758,11 +758,44 @@ def test_sweep_matches_plain_kernel_and_oracle(ctx6, o6, torch):
                              inv_sigma2=dv(w).repeat(n))
     torch.cuda.synchronize()
     assert torch.equal(g_sw["grad"], g_pl["grad"]) and torch.equal(g_sw["chi2"], g_pl["chi2"])
+    # the persistent launch (each workgroup striding over several samples): bitwise the same
+    chi_ps = ctx6.bandflux(**P, t=t, band=band, broadcast="persistent", chi2=True, data=dv(data), inv_sigma2=dv(w))
+    flux_ps = ctx6.bandflux(**P, t=t, band=band, broadcast="persistent")
+    g_ps = ctx6.bandflux_vjp(**P, t=t, band=band, broadcast="persistent", chi2=True, data=dv(data),
+                             inv_sigma2=dv(w))
+    ctx6.device_check()
+    assert torch.equal(chi_ps, chi_sw) and torch.equal(flux_ps, flux_sw)
+    assert torch.equal(g_ps["grad"], g_sw["grad"]) and torch.equal(g_ps["chi2"], g_sw["chi2"])
+
+
+def test_persistent_sweep_with_fewer_samples_than_workgroups(ctx6, torch, sb):
+    """Seven and 4,099 samples (grids of one workgroup per sample, the grid's cap not reached): the
+    persistent sweep equals the one-workgroup-per-sample sweep; SB_PERSISTENT without
+    SB_OBS_BROADCAST is an argument error.  Workgroups striding over several samples are checked at
+    full size (test_sweep_full_size_sampled: 1,048,576 samples, 16 per workgroup on an MI355X)."""
+    sw = synth.sweep_120_obs(n_samples=4099)
+    smp = sw.samples
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    t, band = dv(sw.obs_t), dv(sw.obs_band)
+    for n in (7, 4099):
+        P = dict(z=dv(smp.z[:n]), t0=dv(smp.t0[:n]), x0=dv(smp.x0[:n]), x1=dv(smp.x1[:n]), c=dv(smp.c[:n]))
+        a = ctx6.bandflux(**P, t=t, band=band, broadcast=True)
+        b = ctx6.bandflux(**P, t=t, band=band, broadcast="persistent")
+        ctx6.device_check()
+        assert torch.equal(a, b), n
+    import ctypes
+    P = dict(z=dv(smp.z[:7]), t0=dv(smp.t0[:7]), x0=dv(smp.x0[:7]), x1=dv(smp.x1[:7]), c=dv(smp.c[:7]))
+    off = torch.zeros(8, dtype=torch.int32, device="cuda")
+    batch = ctx6._batch(P["z"], P["t0"], P["x0"], P["x1"], P["c"], t, band, off, False, None, None, False)
+    batch.flags = sb.SB_PERSISTENT
+    out = torch.empty(len(sw.obs_t), device="cuda")
+    assert sb.lib().sb_bandflux(ctx6._h, ctypes.byref(batch), ctypes.c_void_p(out.data_ptr()), None) == sb.SB_ERR_ARG
 
 
 def test_sweep_full_size_sampled(ctx6, o6, torch):
     """The full sweep (1,048,576 samples x 120 observations) as the benchmark launches it, chi-square
-    and flux outputs: 256 seeded samples against the oracle, and every chi-square finite."""
+    and flux outputs: 256 seeded samples against the oracle, every chi-square finite, and the
+    persistent launch's chi-squares bitwise those of the one-workgroup-per-sample launch."""
     print("case: full sweep 1048576 x 120", flush=True)
     sw = synth.sweep_120_obs()
     smp = sw.samples
@@ -772,8 +805,10 @@ def test_sweep_full_size_sampled(ctx6, o6, torch):
     P = dict(z=dv(smp.z), t0=dv(smp.t0), x0=dv(smp.x0), x1=dv(smp.x1), c=dv(smp.c))
     t, band = dv(sw.obs_t), dv(sw.obs_band)
     chi = ctx6.bandflux(**P, t=t, band=band, broadcast=True, chi2=True, data=dv(data), inv_sigma2=dv(w))
+    chi_ps = ctx6.bandflux(**P, t=t, band=band, broadcast="persistent", chi2=True, data=dv(data), inv_sigma2=dv(w))
     flux = ctx6.bandflux(**P, t=t, band=band, broadcast=True)
     ctx6.device_check()
+    assert torch.equal(chi, chi_ps)
     C = chi.cpu().numpy()
     assert np.all(np.isfinite(C))
     pick = np.sort(np.random.default_rng(77).choice(n, 256, replace=False))

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2504_08081_amd", "csrc")
 
 
-@pytest.mark.parametrize("src", ["sb_bandflux.hip", "sb_fit.hip"])
+@pytest.mark.parametrize("src", ["sb_bandflux.hip", "sb_fit.hip", "sb_probe.hip"])
 def test_no_barrier_in_per_lane_loop(src, tmp_path):
     asm = device_asm(os.path.join(CSRC, src), str(tmp_path / "k.s"))
     if "s_barrier" not in asm:
