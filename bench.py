@@ -278,7 +278,7 @@ def cpu_baseline_isolated(batch, truth, model, bands, budget_s):
 
 # ----------------------------------------------------------------------------- HBM traffic from counters
 
-PROFILE_VJP = os.path.join(ROOT, "profiles", "k_sn_vjp_4096sn.md")
+PROFILE_VJP = os.path.join(ROOT, "profiles", "k_band_vjp_4096sn.md")
 
 
 def code_only(text):
@@ -444,7 +444,7 @@ def main():
     prof = profile_record(PROFILE_VJP)
     if "executed_flops" in prof:
         flops, src = prof["executed_flops"], ("executed FP32 flops per launch (FMA 2, add and mul 1, 64 lanes) from "
-                                              "the rocprofv3 counters of the same kernels, profiles/k_sn_vjp_4096sn.md")
+                                              "the rocprofv3 counters of the same kernels, profiles/k_band_vjp_4096sn.md")
     else:
         flops, src = alg_flops, "implemented algorithm's flop count (no counter profile of the current kernels)"
     achieved = flops / kern_s / 1e12
@@ -456,7 +456,8 @@ def main():
                    "n_sn": truth.n_sn, "n_obs": n_obs, "bands": 6, "surface": "71x721", "parallelism": "none"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": prof.get("traffic"),
-                     "achieved_source": src, "kernel": "k_sn<VJP>", "kernel_ms": float(durs.mean()),
+                     "achieved_source": src, "kernel": "k_band<VJP> + k_band_sum (one call)",
+                     "kernel_ms": float(durs.mean()),
                      "kernel_ms_median": float(np.median(durs)),
                      "flops_per_launch": flops,
                      "attainable_peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,

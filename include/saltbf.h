@@ -216,7 +216,14 @@ sb_status sb_bandflux(sb_ctx *ctx, const sb_batch *batch, float *out, void *hip_
  * grad is required ([n_sn*5]); flux_out ([n_obs], or [n_sn][n_obs] with
  * broadcast), jac_out ([n_obs][5], or [n_sn][n_obs][5]) and chi2_out ([n_sn],
  * SB_OUT_CHI2 only) may be NULL.  Each supernova's sums are reduced in a fixed
- * order by one workgroup: results are bitwise reproducible. */
+ * order (with at most 8 bands registered: per band over one wave's lanes, then over
+ * its bands in band order by one thread; otherwise by one workgroup): results are
+ * bitwise reproducible and do not depend on the rest of the batch.  With at most 8
+ * bands the per-band sums live in a device workspace the context keeps per stream
+ * (24 bytes per supernova and registered band), grown on demand: a call that must
+ * grow it waits for the stream's earlier work, and is SB_ERR_STATE while the stream
+ * is being captured into a graph (one call of the same size before the capture
+ * sizes it). */
 sb_status sb_bandflux_vjp(sb_ctx *ctx, const sb_batch *batch, const float *cotangent, float *grad,
                           float *flux_out, float *jac_out, float *chi2_out, void *hip_stream);
 

@@ -135,14 +135,17 @@ __device__ void sn_body(const KModel& m, const KTables& tb, const KBatch& b, int
       } else {
         float wp[4];
         cr_weights(pc.x, pc.edge, wp);
-        const int tb0 = pc.edge ? 1 : 0, tb1 = pc.edge ? 3 : 4;
+        // all four taps (an edge cell's outer weights are zero and add exact zeros; the
+        // clamped rows are rows the band wrote), so the loop unrolls
         float Sx = 0.f;
         if constexpr (MODE == FWD) {
-          for (int t = tb0; t < tb1; ++t) Sx = fmaf(wp[t], Rb[row_clamp(pc.a - 1 + t, rlo, rhi) * NR], Sx);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) Sx = fmaf(wp[t], Rb[row_clamp(pc.a - 1 + t, rlo, rhi) * NR], Sx);
           f = A * Sx;
         } else {
           float S1 = 0.f, Sc = 0.f, Sl = 0.f, Sp = 0.f;
-          for (int t = tb0; t < tb1; ++t) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
             const float* r = Rb + row_clamp(pc.a - 1 + t, rlo, rhi) * NR;
             Sx = fmaf(wp[t], r[0], Sx);
             S1 = fmaf(wp[t], r[1], S1);
@@ -252,6 +255,219 @@ __global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(5))) 
   }
 }
 
+// ------------------------------------------------------------ adjoint by band
+//
+// With few bands registered the adjoint runs one wave per (supernova, band): its
+// workgroups are a sixth of a supernova's, so a batch of a few thousand supernovae
+// fills the GPU with many short workgroups instead of a few long ones whose last
+// round leaves compute units idle.  Wave (s, b) scans supernova s's observations
+// for band b (the row range its phases touch, and the first and last such
+// observation), builds the band's row projections with band_rows, finishes every
+// observation of the band, and writes its six sums (gradient and chi2), summed
+// over its lanes in a fixed order, to part[s][b].  k_band_sum then adds the bands'
+// sums in band order: one writer per supernova, no float atomics, and every result
+// independent of the rest of the batch and of the launch shape.  Observations
+// whose band id is out of range are the band-0 wave's (NaN and the range flag).
+
+__device__ inline int wave_min_i(int x) {
+  for (int o = 1; o < WAVE; o <<= 1) x = min(x, __shfl_xor(x, o, WAVE));
+  return x;
+}
+__device__ inline int wave_max_i(int x) {
+  for (int o = 1; o < WAVE; o <<= 1) x = max(x, __shfl_xor(x, o, WAVE));
+  return x;
+}
+
+// Dynamic LDS of a band workgroup: one wave's scratch and one band's row projections.
+__host__ __device__ inline size_t band_lds_bytes(const KModel& m, int max_pts, int jcap) {
+  return wave_scratch_bytes<VJP>(max_pts, jcap) + (size_t)m.n_phase * ModeInfo<VJP>::NR * sizeof(float);
+}
+
+template <bool BCAST>
+__device__ void band_body(const KModel& m, const KTables& tb, const KBatch& b, int item, int nb, const Lds& L) {
+  constexpr int NR = ModeInfo<VJP>::NR;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int sn = uni(item / nb), bd = uni(item - sn * nb);
+  const bool chi2 = (b.flags & SB_OUT_CHI2) != 0;
+  const float z = b.z[sn], t0 = b.t0[sn], x0 = b.x0[sn], x1 = b.x1[sn], c = b.c[sn];
+  const double s64 = 1.0 / (1.0 + (double)z);
+  const float s = (float)s64;
+  const float A = (float)((double)x0 * s64);
+  const float qnan = __builtin_nanf("");
+
+  int lo = 0, hi = b.n_obs;
+  bool csr_bad = false;
+  if (!BCAST) {
+    lo = b.off[sn];
+    hi = b.off[sn + 1];
+    if (lo < 0 || hi < lo || hi > b.n_obs) {
+      csr_bad = true;
+      lo = hi = 0;
+    }
+  }
+  lo = uni(lo);
+  hi = uni(hi);
+  const size_t obase = BCAST ? (size_t)sn * (size_t)b.n_obs : 0;
+
+  // the lane's sums start with the scan's chi-square terms (c2) and a NaN for
+  // observations that cannot be evaluated (bad); two registers, not six, stay live
+  // through band_rows
+  float c2 = 0.f;
+  bool bad = false;
+  if (csr_bad && bd == 0) {
+    if (lane == 0) atomicOr(b.err, EFLAG_CSR);
+    bad = true;
+  }
+
+  // scan: the band's observations, the rows their phases touch; observations with
+  // nothing to integrate (their chi-square terms join the lane's sums)
+  int rlo = INT_MAX, rhi = -1, first = INT_MAX, last = -1;
+  for (int i = lo + lane; i < hi; i += WAVE) {
+    const int bi = b.band[i];
+    if ((unsigned)bi >= (unsigned)m.n_bands) {
+      if (bd == 0) {
+        atomicOr(b.err, EFLAG_BAND);
+        const float dn[5] = {qnan, qnan, qnan, qnan, qnan};
+        write_obs<VJP>(b, obase + i, qnan, dn);
+        bad = true;
+      }
+      continue;
+    }
+    if (bi != bd) continue;
+    const PhaseCell pc = phase_cell(b.t[i], t0, s64, m);
+    if (pc.nan) {
+      const float dn[5] = {qnan, qnan, qnan, qnan, qnan};
+      write_obs<VJP>(b, obase + i, qnan, dn);
+      bad = true;
+      continue;
+    }
+    if (!pc.in) {
+      const float d0[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+      write_obs<VJP>(b, obase + i, 0.f, d0);
+      if (chi2) {
+        const float r = -b.data[i];
+        c2 = fmaf(r * r, b.w[i], c2);
+      }
+      continue;
+    }
+    rlo = min(rlo, pc.r0);
+    rhi = max(rhi, pc.r1);
+    first = min(first, i);
+    last = max(last, i);
+  }
+  rlo = uni(wave_min_i(rlo));
+  rhi = uni(wave_max_i(rhi));
+  first = uni(wave_min_i(first));
+  last = uni(wave_max_i(last));
+
+  // acc: gradient (z, t0, x0, x1, c) and chi2
+  float acc[6];
+  if (rhi >= 0) {
+    const bool ok = band_rows<VJP>(m, tb, bd, s64, c, x1, rlo, rhi, L, L.R);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) acc[q] = bad ? qnan : 0.f;
+    acc[5] = bad ? qnan : c2;
+    if (!ok && lane == 0) atomicOr(b.err, EFLAG_WINDOW);
+    const float* Rb = L.R;
+    // every observation of the band, between the first and the last one found
+    for (int i = first + lane; i <= last; i += WAVE) {
+      if (b.band[i] != bd) continue;
+      const PhaseCell pc = phase_cell(b.t[i], t0, s64, m);
+      if (!pc.in) continue;
+      float f, dv[5];
+      if (!ok) {
+        f = qnan;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) dv[q] = qnan;
+      } else {
+        float wp[4];
+        cr_weights(pc.x, pc.edge, wp);
+        // all four taps, as in sn_body
+        float Sx = 0.f, S1 = 0.f, Sc = 0.f, Sl = 0.f, Sp = 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const float* r = Rb + row_clamp(pc.a - 1 + t, rlo, rhi) * NR;
+          Sx = fmaf(wp[t], r[0], Sx);
+          S1 = fmaf(wp[t], r[1], S1);
+          Sc = fmaf(wp[t], r[2], Sc);
+          Sl = fmaf(wp[t], r[3], Sl);
+        }
+        // the phase derivative on the projected phase differences Rd (rows rlo .. rhi-1)
+        float e[3];
+        cr_diff_weights(pc.x, pc.edge, e);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) Sp = fmaf(e[t], Rb[row_clamp(pc.a - 1 + t, rlo, rhi - 1) * NR + 4], Sp);
+        Sp *= m.inv_dphase;
+        f = A * Sx;
+        const float As = A * s;
+        dv[0] = -s * f - As * fmaf(pc.p, Sp, Sl);   // z
+        dv[1] = -As * Sp;                           // t0
+        dv[2] = s * Sx;                             // x0
+        dv[3] = A * S1;                             // x1
+        dv[4] = A * Sc;                             // c
+      }
+      write_obs<VJP>(b, obase + i, f, dv);
+      float gbar;
+      if (chi2) {
+        const float r = f - b.data[i];
+        const float wi = b.w[i];
+        acc[5] = fmaf(r * r, wi, acc[5]);
+        gbar = 2.f * r * wi;
+      } else {
+        gbar = b.cot[obase + i];
+      }
+#pragma unroll
+      for (int q = 0; q < 5; ++q) acc[q] = fmaf(gbar, dv[q], acc[q]);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) acc[q] = bad ? qnan : 0.f;
+    acc[5] = bad ? qnan : c2;
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) acc[q] = wave_sum(acc[q]);
+  if (lane == 0) {
+    float* p = b.part + (size_t)item * PART_WORDS;
+#pragma unroll
+    for (int q = 0; q < PART_WORDS; ++q) p[q] = acc[q];
+  }
+  // the next item's band_rows rewrites the scratch this item's observation pass read
+  wave_sync();
+}
+
+// Items (supernova, band) = (it div nb, it mod nb) for it = g, g + G, ... (G the grid;
+// one item per workgroup unless the launch is persistent), XCD-contiguous.
+template <bool BCAST>
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(5))) void k_band(KModel m, KTables tb, KBatch b,
+                                                                                       int nb) {
+  extern __shared__ __align__(16) char smem[];
+  const Lds L = lds_carve<VJP, 1>(smem, m, tb, 0);
+  const int n_items = uni(b.n_sn * nb), step = uni((int)gridDim.x);
+  for (int it = uni((int)blockIdx.x); it < n_items; it += step)
+    band_body<BCAST>(m, tb, b, xcd_item(it, n_items), nb, L);
+}
+
+// Component q of supernova s's gradient (q < 5) or its chi2 (q = 5), one thread per
+// (s, q): the bands' sums, all loaded at once, added in band order.
+__global__ __launch_bounds__(256) void k_band_sum(const float* __restrict__ part, int n_sn, int nb,
+                                                  float* __restrict__ grad, float* __restrict__ chi2) {
+  const int id = blockIdx.x * 256 + threadIdx.x;
+  if (id >= n_sn * PART_WORDS) return;
+  const int sn = id / PART_WORDS, q = id - sn * PART_WORDS;
+  const float* p = part + (size_t)sn * nb * PART_WORDS + q;
+  float v[BAND_SPLIT_MAX];
+#pragma unroll
+  for (int k = 0; k < BAND_SPLIT_MAX; ++k) v[k] = k < nb ? p[k * PART_WORDS] : 0.f;
+  float g = 0.f;
+#pragma unroll
+  for (int k = 0; k < BAND_SPLIT_MAX; ++k)
+    if (k < nb) g += v[k];
+  if (q < SB_N_PARAMS)
+    grad[(size_t)sn * SB_N_PARAMS + q] = g;
+  else if (chi2)
+    chi2[sn] = g;
+}
+
 size_t lds_bytes(const KModel& m, int max_pts, int jcap, bool adj) {
   return adj ? lds_layout_bytes<VJP>(m.n_phase, max_pts, jcap, 1)
              : lds_layout_bytes<FWD>(m.n_phase, max_pts, jcap, 1);
@@ -328,8 +544,36 @@ constexpr int FLUX_NW = 3;
 // (OBS_NT in sn_body), so every result is bit for bit that of the batch kernel.
 constexpr int FEW_SN_VJP_NW = ModeInfo<VJP>::GROUP;
 
+// The adjoint by band (b.part set by the host): k_band over every (supernova, band),
+// or a persistent grid of them, then k_band_sum.
+template <bool BCAST>
+static hipError_t launch_band_t(const KModel& m, const KTables& tb, const KBatch& b, hipStream_t st) {
+  const int nb = m.n_bands;
+  const int items = b.n_sn * nb;
+  const size_t lds = band_lds_bytes(m, tb.max_pts, tb.jcap);
+  hipError_t e = prep_lds(k_band<BCAST>, lds);
+  if (e != hipSuccess) return e;
+  int grid = items;
+  if (b.flags & SB_PERSISTENT) {
+    int dev = 0, n_cu = 0, per_cu = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_band<BCAST>, WAVE, lds);
+    if (e != hipSuccess) return e;
+    const long long slots = (long long)(per_cu > 0 ? per_cu : 1) * (n_cu > 0 ? n_cu : 1) * PERSIST_ROUNDS;
+    grid = (int)(slots < items ? slots : items);
+  }
+  hipLaunchKernelGGL((k_band<BCAST>), dim3(grid), dim3(WAVE), lds, st, m, tb, b, nb);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_band_sum, dim3((b.n_sn * PART_WORDS + 255) / 256), dim3(256), 0, st, (const float*)b.part,
+                     b.n_sn, nb, b.grad, b.chi2);
+  return hipGetLastError();
+}
+
 hipError_t launch_sn(bool adj, const KModel& m, const KTables& tb, const KBatch& b, hipStream_t st) {
   const bool bc = (b.flags & SB_OBS_BROADCAST) != 0;
+  if (adj && b.part) return bc ? launch_band_t<true>(m, tb, b, st) : launch_band_t<false>(m, tb, b, st);
   if (bc && (b.flags & SB_PERSISTENT)) return adj ? launch_sweep<VJP>(m, tb, b, st) : launch_sweep<FWD>(m, tb, b, st);
   if (adj && !bc && b.n_sn <= FEW_SN) {
     const size_t lds = lds_layout_bytes<VJP>(m.n_phase, tb.max_pts, tb.jcap, FEW_SN_VJP_NW);

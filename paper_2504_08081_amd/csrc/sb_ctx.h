@@ -4,6 +4,7 @@
 #include <atomic>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "sb_internal.h"
@@ -43,6 +44,14 @@ struct sb_ctx {
   size_t max_lds = 65536;
   std::mutex mu;                       // band registration, server start
   sbh::Server* server = nullptr;
+  // per-stream device workspace (the adjoint's per-band partial sums): calls on one stream
+  // run in order, so each stream keeps one buffer, grown on demand
+  struct Workspace {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+  };
+  std::mutex ws_mu;
+  std::unordered_map<void*, Workspace> ws;
 
   sbk::KTables tables() const {
     sbk::KTables t;

@@ -94,9 +94,10 @@ __device__ void fit_eval(const KModel& m, const KTables& tb, const KFit& F, cons
         float wp[4], dw[4];
         cr_weights(pc.x, pc.edge, wp);
         cr_dweights(pc.x, pc.edge, dw);
-        const int tb0 = pc.edge ? 1 : 0, tb1 = pc.edge ? 3 : 4;
+        // all four taps (an edge cell's outer weights are zero and add exact zeros), unrolled
         float Sx = 0.f, Sp = 0.f, S1 = 0.f, Sc = 0.f;
-        for (int t = tb0; t < tb1; ++t) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
           const float* r = Rb + row_clamp(pc.a - 1 + t, rlo, rhi) * NR;
           Sx = fmaf(wp[t], r[0], Sx);
           Sp = fmaf(dw[t], r[0], Sp);

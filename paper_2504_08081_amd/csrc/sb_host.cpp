@@ -183,6 +183,8 @@ sb_status sb_band_grid(const double* wave, const double* trans, int32_t n, doubl
 
 static void free_ctx(sb_ctx* c) {
   if (!c) return;
+  for (auto& kv : c->ws)
+    if (kv.second.ptr) (void)hipFree(kv.second.ptr);
   if (c->d_surf) (void)hipFree(c->d_surf);
   if (c->d_pts) (void)hipFree(c->d_pts);
   if (c->d_npts) (void)hipFree(c->d_npts);
@@ -416,11 +418,52 @@ static sbk::KBatch make_kbatch(sb_ctx* ctx, const sb_batch* b) {
   return k;
 }
 
+// The stream's workspace, at least `bytes` long; the caller holds ctx->ws_mu until its
+// launches that use the buffer are enqueued (so no other thread can replace the buffer
+// in between).  Growing it waits for the stream's earlier work (which may still use the
+// old buffer) and allocates, so it is refused while the stream is being captured into a
+// graph: one call of the same size before the capture sizes it.
+static sb_status stream_workspace(sb_ctx* ctx, hipStream_t st, size_t bytes, void** out) {
+  sb_ctx::Workspace& w = ctx->ws[(void*)st];
+  if (w.bytes >= bytes) {
+    *out = w.ptr;
+    return SB_OK;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(st, &cs);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone)
+    return set_error(SB_ERR_STATE, "sb_bandflux_vjp: the stream's workspace must grow, which cannot happen during "
+                                   "graph capture: make one call of this size on the stream before capturing");
+  if (w.ptr) {
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    (void)hipFree(w.ptr);
+    w.ptr = nullptr;
+    w.bytes = 0;
+  }
+  const size_t want = std::max(bytes, (size_t)1 << 16);
+  if ((e = hipMalloc(&w.ptr, want)) != hipSuccess) {
+    w.ptr = nullptr;
+    return set_error(SB_ERR_NOMEM, std::string("sb_bandflux_vjp: workspace: ") + hipGetErrorString(e));
+  }
+  w.bytes = want;
+  *out = w.ptr;
+  return SB_OK;
+}
+
 static sb_status launch(sb_ctx* ctx, bool adj, sbk::KBatch& kb, hipStream_t st) {
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   const size_t lds = sbk::lds_bytes(ctx->km, ctx->max_pts, ctx->jcap, adj);
   if (lds > ctx->max_lds) return set_error(SB_ERR_ARG, "bands too large for LDS");
+  std::unique_lock<std::mutex> lk(ctx->ws_mu, std::defer_lock);
+  if (adj && ctx->n_bands <= sbk::BAND_SPLIT_MAX) {
+    lk.lock();
+    void* p = nullptr;
+    const sb_status s = stream_workspace(ctx, st, sbk::band_part_bytes(kb.n_sn, ctx->n_bands), &p);
+    if (s != SB_OK) return s;
+    kb.part = (float*)p;
+  }
   e = sbk::launch_sn(adj, ctx->km, ctx->tables(), kb, st);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return SB_OK;

@@ -54,7 +54,17 @@ struct KBatch {
   const float *data, *w, *cot;
   float *flux, *grad, *jac, *chi2;
   int* err;
+  float* part;   // adjoint by band: [n_sn][n_bands][6] partial sums (workspace), or null
 };
+
+// The adjoint runs one wave per (supernova, band) and sums the bands' partials in a
+// second kernel when at most this many bands are registered (the batch kernel
+// launches a workgroup for every registered band of every supernova).
+constexpr int BAND_SPLIT_MAX = 8;
+constexpr int PART_WORDS = 6;     // per (supernova, band): the five gradient sums and chi2
+inline size_t band_part_bytes(int n_sn, int n_bands) {
+  return (size_t)n_sn * (size_t)n_bands * PART_WORDS * sizeof(float);
+}
 
 // Dynamic LDS bytes of the per-supernova pipeline in its smallest form (one
 // wave per workgroup); launches use more waves where they fit in tb.lds_limit.
